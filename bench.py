@@ -1,0 +1,141 @@
+"""Benchmark of the hot path on one MI355X.
+
+One bench step = one full adaptive integration of the single large instance
+(M = 65536, rank-3 kernel (i/j)^a + (j/i)^a + 2 with a = 0.45, lam = 0.005,
+monodisperse start, Dormand-Prince 5(4) with PI control, rtol 1e-6,
+atol 1e-12, t = 0 -> 1e4): every right-hand side, stage combination, error
+norm and controller decision of the run.  value = accepted RK steps per
+second over the timed runs; ms_per_step = time-to-t_end of one run.
+
+Prints ONE JSON line.  Inputs are synthetic and built on the host, then
+moved to HBM before the timed region.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peak HBM3E bandwidth (bytes/s)
+HBM_PEAK = 8.0e12
+
+
+def rhs_bytes(M, R, L):
+    """Algorithmic HBM bytes of the three right-hand-side kernels (FP64):
+    column pass reads y, U, V and writes R packed spectra; the row-pair pass
+    reads them and writes the packed half-length inverse input; the inverse
+    column pass reads that plus y and U and writes S."""
+    a = 8 * M + 16 * M * R + 16 * L * R
+    b = 16 * L * R + 8 * L
+    c = 8 * L + 8 * M + 8 * M * R + 8 * M
+    return {"phase_a": a, "phase_b": b, "phase_c": c, "rhs": a + b + c}
+
+
+def cpu_baseline(U, V, lam, n0, per_step_rhs):
+    """The FP64 oracle (plain O(M^2) direct sums) timed on the host: one full
+    right-hand side at the start state, converted to DP5 steps/s."""
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    oracle.lib()
+    t0 = time.perf_counter()
+    oracle.rhs(U, V, lam, n0, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / (per_step_rhs * dt), "unit": "accepted steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"one direct O(M^2 R) right-hand side at M={n0.size} "
+                      f"({dt:.2f} s), times {per_step_rhs} per DP5 step"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--t-end", type=float, default=None, help="shorter runs (profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU sharding is described in DESIGN.md, not run", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2407_16559_amd as smol
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    c = W.CONFIGS[2]
+    t_end = args.t_end if args.t_end else c["t_end"]
+    U, V, lam, n0 = W.config_instance(2)
+    M, R = U.shape[1], U.shape[0]
+    Ud = torch.from_numpy(U).to(dev)
+    Vd = torch.from_numpy(V).to(dev)
+    n0d = torch.from_numpy(n0).to(dev)
+    out = torch.empty_like(n0d)
+
+    def run():
+        return smol.integrate(Ud, Vd, lam, n0d, t_end, c["rtol"], c["atol"], method="dp5",
+                              out=out, raise_on_error=True)
+
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stats.append(run()[1])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    n_acc = sum(s["n_accept"] for s in stats)
+    n_rhs = sum(s["n_rhs"] for s in stats)
+
+    # live per-kernel timing of one right-hand side (HIP events on the stream
+    # the kernels run on), at the run's final state
+    logL = int(np.ceil(np.log2(2 * M - 2)))
+    L = 1 << logL
+    prof = smol.profile_rhs(Ud, Vd, lam, out.clone(), iters=200)
+    nbytes = rhs_bytes(M, R, L)
+    dom = max(("phase_a", "phase_b", "phase_c"), key=lambda k: prof[k])
+    achieved = nbytes[dom] / (prof[dom] * 1e-3)
+    roof = {"bound": "hbm", "kernel": dom, "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None,
+            "ms_per_launch": {k: prof[k] for k in ("phase_a", "phase_b", "phase_c")},
+            "rhs_ms": prof["rhs"],
+            "rhs_alg_bytes": nbytes["rhs"],
+            "rhs_frac": nbytes["rhs"] / (prof["rhs"] * 1e-3) / HBM_PEAK}
+
+    line = {
+        "metric": "accepted RK steps/s (time-to-t_end at rtol 1e-6), M=2^16 R=3",
+        "value": n_acc / elapsed,
+        "unit": "accepted steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "single-large-oscillatory: M=65536, R=3 kernel (i/j)^a+(j/i)^a+2, "
+                               f"a=0.45, lam=0.005, monodisperse start, DP5(4) PI, rtol=1e-6, "
+                               f"atol=1e-12, t_end={t_end:g}",
+                   "M": M, "R": R, "fft_length": L, "parallelism": "1 GPU"},
+        "time_to_t_end_s": elapsed / args.steps,
+        "accepted_steps_per_run": stats[-1]["n_accept"],
+        "rejected_steps_per_run": stats[-1]["n_reject"],
+        "rhs_evals_per_s": n_rhs / elapsed,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(U, V, lam, n0, 6)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

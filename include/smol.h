@@ -1,0 +1,203 @@
+/*
+ * smol.h -- C ABI of libsmol, an MI355X (gfx950) solver for the truncated
+ * aggregation-shattering Smoluchowski system with a low-rank kernel.
+ *
+ * Method: Matveev, Zhilin, Smirnov, "Adaptive time-stepping for
+ * aggregation-shattering kinetics" (arXiv 2407.16559).
+ *
+ * Conventions shared by every entry point
+ *   - Sizes s = 1..M are stored at index s-1.
+ *   - The kernel K_{ij} = sum_{a<R} U_{i a} V_{a j} (Sec. 1, display after
+ *     Eq. (2)).  Both factors are stored alpha-major as R x M row-major
+ *     arrays: U[a*M + i-1] and V[a*M + j-1], FP64.
+ *   - Array arguments are DEVICE pointers owned by the caller (for example
+ *     torch tensors' data_ptr()).  The library never frees caller memory.
+ *     It owns only cached plans and workspaces, keyed by (device, M, R,
+ *     precision), which smol_release_plans() frees.
+ *   - `stream` is a hipStream_t; NULL means the null stream.
+ *   - Every call returns an int status (SMOL_OK or a negative code) and
+ *     never throws across the ABI.  smol_strerror() names a code.
+ *   - Calls are not re-entrant for the same plan from several host threads.
+ */
+#ifndef SMOL_H
+#define SMOL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SMOL_OK = 0,
+    SMOL_EINVAL = -1,      /* bad size, pointer, tolerance, lambda or option */
+    SMOL_ENOMEM = -2,      /* device allocation failed */
+    SMOL_EDEVICE = -3,     /* a HIP call failed */
+    SMOL_ESTEPSIZE = -4,   /* step fell below max(h_min, 10 ulps of t) */
+    SMOL_EMAXSTEPS = -5,   /* step-attempt limit reached */
+    SMOL_ENONFINITE = -6,  /* NaN/Inf in the state or a NaN error norm */
+    SMOL_EUNSUPPORTED = -7 /* valid request this build does not provide */
+};
+
+/* Embedded Runge--Kutta pairs (both first-same-as-last). */
+enum { SMOL_BS32 = 0, SMOL_DP54 = 1 };
+
+/* Arithmetic of the convolution part of the right-hand side. */
+enum { SMOL_FP64 = 0, SMOL_FP32X2 = 1 };
+
+/* Step-size controller. */
+enum { SMOL_CTRL_PI = 0, SMOL_CTRL_LEARNED = 1 };
+
+typedef struct {
+    int64_t n_rhs;     /* right-hand-side evaluations, including the two of
+                          the starting-step procedure */
+    int64_t n_accept;  /* accepted steps */
+    int64_t n_reject;  /* rejected step attempts */
+    double t;          /* time reached (== t_end on success) */
+    double h;          /* next proposed step */
+    double err;        /* weighted-RMS error norm of the last attempt */
+    int32_t status;    /* SMOL_OK or the code that ended the run */
+    int32_t n_fallback;/* learned controller: steps that fell back to PI */
+} smol_stats;
+
+/*
+ * smol_rhs -- dndt = S(n), the right-hand side of the truncated
+ * aggregation-shattering system (Sec. 1, Eq. (2) with the shattering terms
+ * of Eq. (4); Sec. 2, Eq. (5) names the operator S):
+ *
+ *   S_1 = -n_1 sum_i K_{1i} n_i + (lam/2) sum_{i,j>=2} (i+j) K_{ij} n_i n_j
+ *         + lam n_1 sum_{j>=2} j K_{1j} n_j
+ *   S_s = (1/2) sum_{i+j=s} K_{ij} n_i n_j - (1+lam) n_s sum_i K_{si} n_i,
+ *         s = 2..M.
+ *
+ * The monomer-j shattering gain carries the factor n_1 (mass balance).
+ * Evaluated in O(M R log M): the birth sums are R linear convolutions done
+ * with FFTs of length L = nextpow2(2M-2), the death and shattering sums are
+ * 4R reductions.
+ *
+ * M >= 1; 1 <= R <= 16; lam >= 0 and finite; n, dndt: M doubles each, on
+ * the device; dndt must not alias n.  precision: SMOL_FP64 or SMOL_FP32X2
+ * (the convolutions in float-float arithmetic, everything else FP64).
+ * Asynchronous on `stream`.  Errors: SMOL_EINVAL, SMOL_ENOMEM,
+ * SMOL_EDEVICE, SMOL_EUNSUPPORTED (M too large for this build).
+ */
+int smol_rhs(int64_t M, int32_t R, const double *U, const double *V,
+             double lambda, const double *n, double *dndt, int32_t precision,
+             void *stream);
+
+/*
+ * smol_integrate -- integrate dn/dt = S(n), n(0) = n0 (Sec. 2, Eq. (5)) to
+ * t_end with an embedded explicit Runge--Kutta pair and adaptive steps
+ * (the accept / retry pattern of Sec. 2): an attempt is accepted when the
+ * weighted-RMS norm
+ *     err = sqrt(mean_s (e_s / (atol + rtol * max(|n_s|, |n_new,s|)))^2)
+ * of the embedded error estimate e is <= 1; the step is then changed by a
+ * PI controller, h *= clamp(0.9 err^-alpha err_prev^beta, 0.2, 10)
+ * (alpha = 0.7/k, beta = 0.4/k, k = embedded order + 1; no growth on the
+ * step right after a rejection); a rejection shrinks h by
+ * max(0.2, 0.9 err^(-1/k)).  The first step comes from Hairer's starting
+ * procedure; the last one is clipped to land exactly on t_end.
+ *
+ * n0, n_out: M doubles on the device (n_out may alias n0).  method:
+ * SMOL_BS32 or SMOL_DP54.  rtol > 0, atol >= 0, t_end >= 0 (t_end == 0
+ * returns n0 after 0 steps).  stats: HOST pointer, may be NULL.
+ * Synchronous: returns after the run with n_out written.  On
+ * SMOL_ESTEPSIZE / SMOL_EMAXSTEPS / SMOL_ENONFINITE, n_out holds the last
+ * accepted state and stats->t < t_end.
+ */
+int smol_integrate(int64_t M, int32_t R, const double *U, const double *V,
+                   double lambda, const double *n0, double t_end, double rtol,
+                   double atol, int32_t method, int32_t precision,
+                   double *n_out, smol_stats *stats, void *stream);
+
+/* Options of smol_integrate_ex; zero-initialise and set what you need. */
+typedef struct {
+    double h0;          /* > 0: first step; 0: starting procedure */
+    double h_min;       /* > 0: smallest allowed step */
+    int64_t max_steps;  /* > 0: limit on step attempts; 0: 10^8 */
+    double alpha, beta; /* PI exponents; alpha <= 0: defaults for both;
+                           alpha > 0: both as given (beta = 0 selects the
+                           pure I controller) */
+    int32_t controller; /* SMOL_CTRL_PI or SMOL_CTRL_LEARNED */
+    int32_t reserved;
+    double *log;        /* device pointer or NULL: one row per attempt,
+                           (t, h, err, accepted, t_after, M0, M1, M2, M3)
+                           as 9 doubles */
+    int64_t log_cap;    /* rows available in log */
+} smol_options;
+
+/* smol_integrate with options.  The number of log rows written is
+ * min(log_cap, n_accept + n_reject). */
+int smol_integrate_ex(int64_t M, int32_t R, const double *U, const double *V,
+                      double lambda, const double *n0, double t_end,
+                      double rtol, double atol, int32_t method,
+                      int32_t precision, const smol_options *opts,
+                      double *n_out, smol_stats *stats, void *stream);
+
+/* One instance of a batched run.  All pointers are device pointers. */
+typedef struct {
+    int64_t M;
+    int32_t R;
+    int32_t reserved;
+    const double *U, *V;
+    double lambda;
+    const double *n0;
+    double *n_out;
+    double t_end, rtol, atol;
+} smol_instance;
+
+/*
+ * smol_integrate_batch -- advance n_inst independent instances (uneven M,
+ * kernels, lambda, tolerances) with per-instance step sizes and
+ * accept/reject, in one persistent launch.  `inst` and `stats` are HOST
+ * arrays of n_inst entries.  A failing instance records its status in its
+ * own stats entry and does not stop the others; the call returns SMOL_OK
+ * when every instance is launched and finishes (check each stats[i].status).
+ */
+int smol_integrate_batch(int32_t n_inst, const smol_instance *inst,
+                         int32_t method, int32_t precision,
+                         const smol_options *opts, smol_stats *stats,
+                         void *stream);
+
+/* Learned step proposer: a 9-64-64-1 tanh MLP in FP32 (4929 parameters,
+ * layout W1[64][9], b1[64], W2[64][64], b2[64], W3[64], b3).  Features:
+ * log M0..log M3 of the state, log h, log err of the last four attempts.
+ * Output: log(h_next / h), clamped to [log 0.2, log 10].  `params` is a
+ * device pointer; the library keeps its own copy per device. */
+int smol_proposer_set(const float *params, int32_t n_params, void *stream);
+
+/* Train the proposer on logged rows with the library's own forward,
+ * backward and Adam kernels (device pointers):
+ *   X[n_rows][9] features, target[n_rows] wanted log step ratio,
+ *   params[4929] in/out, loss_out[epochs] mean weighted-MSE per epoch
+ *   (over-predictions weighted by over_weight). */
+int smol_proposer_train(const float *X, const float *target, int64_t n_rows,
+                        float *params, int32_t epochs, int32_t batch,
+                        float lr, float over_weight, uint64_t seed,
+                        float *loss_out, void *stream);
+
+/* Timing hook for benchmarks.  Same arguments as smol_rhs (FP64), plus:
+ * iters >= 1 launches of each of the three kernels of one right-hand side
+ * -- the column pass, the row-pair spectral pass, the inverse column pass
+ * with the finish -- back to back, each kernel's batch bracketed by HIP
+ * events on `stream`; then iters whole right-hand sides.  ms_out (HOST, 4
+ * floats) receives the mean milliseconds per launch of each kernel and per
+ * whole right-hand side.  dndt holds S(n) afterwards.  Synchronous. */
+int smol_profile_rhs(int64_t M, int32_t R, const double *U, const double *V,
+                     double lambda, const double *n, double *dndt,
+                     int32_t iters, float *ms_out, void *stream);
+
+/* Free cached plans and workspaces on the current device. */
+int smol_release_plans(void);
+
+/* Static string naming a status code. */
+const char *smol_strerror(int code);
+
+/* Library version string. */
+const char *smol_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMOL_H */

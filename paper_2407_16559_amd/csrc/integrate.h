@@ -1,0 +1,202 @@
+// Embedded explicit Runge--Kutta integration of dn/dt = S(n) (Sec. 2,
+// Eq. (5)) with adaptive steps, as kernels that read a device-resident
+// control block.  One step attempt is a fixed kernel sequence
+//     [A_i B_i C_i] for stages i = 2..S, then the controller,
+// so it is captured once as a hipGraph and replayed; once the run is done
+// every kernel returns at entry, which makes surplus replays no-ops.
+//
+// Stage i computes k_i = S(y_i).  The stage state y_{i+1} = n + h sum_j
+// a_{i+1,j} k_j and its four reductions are produced in the epilogue of
+// stage i's finish (phase C), so phase A of stage i+1 only reads y; stage 2
+// forms y_2 = n + h a_21 k_1 in its phase A because h is only known after
+// the controller.  The last stage state is the propagated solution (FSAL),
+// written straight into the second state buffer; the last finish also
+// accumulates the weighted-RMS error norm and the moments of n_new.
+#pragma once
+#include "rhs.h"
+
+// Status codes, mirrored from smol.h for device code.
+#define ST_OK 0
+#define ST_ESTEPSIZE (-4)
+#define ST_EMAXSTEPS (-5)
+#define ST_ENONFINITE (-6)
+
+struct Tableau {
+    int S;             // stages including the FSAL stage
+    int q;             // order of the embedded solution
+    double a[8][8];    // a[i][j], 0-based
+    double d[8];       // b_j - bhat_j
+};
+
+// Bogacki & Shampine (1989) 3(2) and Dormand & Prince (1980) 5(4).
+__constant__ Tableau c_tab[2] = {
+    {4, 2,
+     {{0}, {1.0 / 2}, {0.0, 3.0 / 4}, {2.0 / 9, 1.0 / 3, 4.0 / 9}},
+     {2.0 / 9 - 7.0 / 24, 1.0 / 3 - 1.0 / 4, 4.0 / 9 - 1.0 / 3, -1.0 / 8}},
+    {7, 4,
+     {{0},
+      {1.0 / 5},
+      {3.0 / 40, 9.0 / 40},
+      {44.0 / 45, -56.0 / 15, 32.0 / 9},
+      {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729},
+      {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656},
+      {35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}},
+     {35.0 / 384 - 5179.0 / 57600, 0.0, 500.0 / 1113 - 7571.0 / 16695, 125.0 / 192 - 393.0 / 640,
+      -2187.0 / 6784 + 92097.0 / 339200, 11.0 / 84 - 187.0 / 2100, -1.0 / 40}},
+};
+
+struct IntegCtl {
+    // problem, written by the host before a run
+    const double *U, *V;
+    double lam, t_end, rtol, atol, h_min, h0_user;
+    double alpha, beta, safety, facmin, facmax;
+    int64_t max_steps;
+    double *log;
+    int64_t log_cap;
+    int32_t method, controller;
+    // dynamic state
+    double t, h, t_new, err, err_prev, min_step, h0;
+    int64_t n_rhs, n_accept, n_reject, attempts;
+    int32_t status, done, cur, kp, rejected, n_fallback;
+    double err_hist[4];
+    int32_t n_hist, use_pi;
+};
+
+struct IntegDev {
+    int64_t M, Mt;
+    int R, logL;
+    double *Ut, *Vt;  // transposed copies of U and V
+    IntegCtl *ctl;
+    double *nb[2];
+    double *kslot[8];
+    double *ybuf;
+    cd *Z, *Qp;
+    double *red_part, *red, *epart;
+    Roots rt;
+    const float *mlp;  // proposer weights (may be null)
+};
+
+__device__ __forceinline__ RhsPlanDev plan_of(const IntegDev &I, const IntegCtl &c)
+{
+    RhsPlanDev P;
+    P.M = I.M;
+    P.R = I.R;
+    P.logL = I.logL;
+    P.logN1 = (I.logL + 1) / 2;
+    P.logN2 = I.logL / 2;
+    P.tr = 1;
+    P.ustride = I.Mt;
+    P.lam = c.lam;
+    P.U = c.U;
+    P.V = c.V;
+    P.Z = I.Z;
+    P.Qp = I.Qp;
+    P.red_part = I.red_part;
+    P.red = I.red;
+    P.rt = I.rt;
+    return P;
+}
+
+// stage j (1-based) vector given the FSAL parity kp
+__device__ __forceinline__ double *kvec(const IntegDev &I, const IntegCtl &c, int S, int j)
+{
+    if (j == 1) return I.kslot[c.kp ? S - 1 : 0];
+    if (j == S) return I.kslot[c.kp ? 0 : S - 1];
+    return I.kslot[j - 1];
+}
+
+// stage codes: 0 = S(n0) for the starting step, 1 = S(n0 + h0 f0), 2..S
+__device__ __forceinline__ Pro stage_pro(const IntegDev &I, const IntegCtl &c, const Tableau &T,
+                                         int stage)
+{
+    const int S = T.S;
+    double *n = I.nb[c.cur];
+    if (stage == 0) return Pro{A_COMBINE, n, nullptr, 0.0, nullptr};
+    if (stage == 1) return Pro{A_COMBINE, n, kvec(I, c, S, 1), c.h0, I.ybuf};
+    if (stage == 2) return Pro{A_COMBINE, n, kvec(I, c, S, 1), c.h * T.a[1][0], I.ybuf};
+    return Pro{A_GIVEN, stage == S ? I.nb[c.cur ^ 1] : I.ybuf, nullptr, 0.0, nullptr};
+}
+
+__device__ inline Epi stage_epi(const IntegDev &I, const IntegCtl &c, const Tableau &T, int stage)
+{
+    const int S = T.S;
+    Epi ep{};
+    ep.n = I.nb[c.cur];
+    ep.h = c.h;
+    ep.rtol = c.rtol;
+    ep.atol = c.atol;
+    ep.epart = I.epart;
+    if (stage == 0) {
+        ep.mode = C_INIT0;
+        ep.y = ep.n;
+        ep.out = kvec(I, c, S, 1);
+    } else if (stage == 1) {
+        ep.mode = C_INIT1;
+        ep.y = I.ybuf;
+        ep.ks[0] = kvec(I, c, S, 1);
+        ep.nks = 1;
+    } else if (stage < S) {
+        ep.mode = C_STAGE;
+        ep.y = I.ybuf;
+        ep.out = kvec(I, c, S, stage);
+        ep.ynext = (stage + 1 == S) ? I.nb[c.cur ^ 1] : I.ybuf;
+        int m = 0;
+        for (int j = 1; j < stage; ++j) {
+            const double a = T.a[stage][j - 1];
+            if (a != 0.0) {
+                ep.ks[m] = kvec(I, c, S, j);
+                ep.coef[m++] = a;
+            }
+        }
+        ep.nks = m;
+        ep.cS = T.a[stage][stage - 1];
+    } else {
+        ep.mode = C_LAST;
+        ep.y = I.nb[c.cur ^ 1];
+        ep.out = kvec(I, c, S, S);
+        int m = 0;
+        for (int j = 1; j < S; ++j) {
+            const double dj = T.d[j - 1];
+            if (dj != 0.0) {
+                ep.ks[m] = kvec(I, c, S, j);
+                ep.coef[m++] = dj;
+            }
+        }
+        ep.nks = m;
+        ep.cS = T.d[S - 1];
+    }
+    return ep;
+}
+
+// Prepare the next attempt (one thread): step-start clamp, limits, t_end clip.
+__device__ inline void prepare_attempt(IntegCtl &c, bool new_step)
+{
+    if (new_step) {
+        double ms = 10.0 * fabs(nextafter(c.t, INFINITY) - c.t);
+        if (c.h_min > ms) ms = c.h_min;
+        c.min_step = ms;
+        if (c.h < ms) c.h = ms;
+    }
+    if (c.attempts >= c.max_steps) {
+        c.status = ST_EMAXSTEPS;
+        c.done = 1;
+        return;
+    }
+    if (!(c.h >= c.min_step)) {
+        c.status = ST_ESTEPSIZE;
+        c.done = 1;
+        return;
+    }
+    double tn = c.t + c.h;
+    if (tn > c.t_end) tn = c.t_end;
+    c.t_new = tn;
+    c.h = tn - c.t;
+}
+
+// Sum njobs partial rows of SMOL_EPART doubles in job order (one thread).
+__device__ inline void sum_epart(const double *ep, int njobs, double *acc)
+{
+    for (int q = 0; q < SMOL_EPART; ++q) acc[q] = 0.0;
+    for (int j = 0; j < njobs; ++j)
+        for (int q = 0; q < SMOL_EPART; ++q) acc[q] += ep[(int64_t)j * SMOL_EPART + q];
+}

@@ -1,0 +1,508 @@
+// The O(M R log M) right-hand side of the truncated aggregation-shattering
+// system (Sec. 1, Eq. (2) and Eq. (4); Sec. 2, Eq. (5)).
+//
+// Birth: with a_al[i] = U_{i al} y_i and b_al[j] = V_{al j} y_j (sizes 1..M-1
+// at indices 0..M-2), (1/2) sum_{i+j=s} K_ij y_i y_j = (1/2) sum_al c_al[s-2]
+// where c_al is the linear convolution a_al * b_al.  All R convolutions are
+// summed in the frequency domain: z_al = a_al + i b_al is transformed with
+// one complex FFT of length L >= 2M-2 (no wrap-around for the outputs used),
+// A = (Z_k + conj Z_{L-k})/2, B = (Z_k - conj Z_{L-k})/(2i), so
+//     P_k = sum_al A_al B_al = sum_al (Z_al,k^2 - conj(Z_al,L-k)^2) / (4i)
+// and c = sum_al c_al = IDFT_L(P), which is real.
+//
+// Death and shattering: four reductions per rank,
+//     w_al = sum_{j>=1} V_{al j} y_j,  t_al = sum_{j>=2} j V_{al j} y_j,
+//     r_al = sum_{i>=2} U_{i al} y_i,  p_al = sum_{i>=2} i U_{i al} y_i,
+// give sum_i K_si y_i = sum_al U_{s al} w_al and, with q_al = w_al - V_{al 1} y_1,
+//     S_1 = -y_1 sum_al U_{1 al} w_al + (lam/2) sum_al (p_al q_al + r_al t_al)
+//           + lam y_1 sum_al U_{1 al} t_al,
+//     S_s = (1/2) c[s-2] - (1 + lam) y_s sum_al U_{s al} w_al,  s >= 2.
+//
+// FFT of length L = N1 * N2 in four steps (index n = N2 n1 + n2, frequency
+// k = k1 + N1 k2), run as three phases separated by grid-wide barriers:
+//   A  column pass: per column n2, DFT over n1 (length N1; rows n1 >= N1/2
+//      are zero padding), times W_L^{n2 k1}; staged through LDS and stored
+//      row-major Z[k1][n2] in segments of several columns.
+//   B  per row pair {k1, N1-k1}: DFT over n2 (length N2) of every rank's two
+//      rows, the spectral product P (rows k1 and N1-k1 hold k and L-k), then
+//      the inverse DFT over k2 times W_L^{-a k1}, with columns a and a+N2/2
+//      packed into one complex value (c is real).
+//   C  per packed column: inverse DFT over k1 (length N1) gives
+//      L (c[a + N2 b] + i c[a + N2/2 + N2 b]); the finish computes S and the
+//      caller's fused epilogue (stage state, error norm, ...), spread over
+//      the whole workgroup.
+//
+// Layouts of the per-size vectors (state, stages, U, V): natural (size s at
+// index s-1) or transposed, where index idx = N2 n1 + n2 < L/2 lives at
+// n2 (N1/2) + n1 and idx = L/2 (only when M - 1 = L/2) at L/2.  In the
+// transposed layout every column pass reads, and every finish writes,
+// contiguous runs; the integrator keeps its vectors that way.
+#pragma once
+#include "fft.h"
+
+enum { A_GIVEN = 0, A_COMBINE = 1 };
+enum { C_RHS = 0, C_STAGE = 1, C_LAST = 2, C_INIT0 = 3, C_INIT1 = 4 };
+#define SMOL_MAX_STAGE 8
+#define SMOL_EPART 8   // doubles per error/moment partial row
+
+struct RhsPlanDev {
+    int64_t M;
+    int R;
+    int logL, logN1, logN2;
+    int tr;               // 1: transposed vector layout
+    int64_t ustride;      // distance between the rank rows of U and V
+    double lam;
+    const double *U, *V;  // alpha-major, rows of ustride
+    cd *Z;                // R * L
+    cd *Qp;               // L / 2
+    double *red_part;     // [jobs][R][4]
+    double *red;          // [R][4]: w, t, r, p
+    Roots rt;
+};
+
+// position of size index idx (0-based) in the transposed layout
+__host__ __device__ __forceinline__ int64_t pos_tr(int64_t idx, int logL)
+{
+    const int logN1 = (logL + 1) / 2, logN2 = logL / 2;
+    const int64_t half = 1LL << (logL - 1);
+    if (idx >= half) return half;
+    return ((idx & ((1LL << logN2) - 1)) << (logN1 - 1)) + (idx >> logN2);
+}
+
+// position of size index idx (0-based) in a vector of the plan's layout
+__device__ __forceinline__ int64_t pos_of(const RhsPlanDev &P, int64_t idx)
+{
+    return P.tr ? pos_tr(idx, P.logL) : idx;
+}
+
+// Phase-A input: y = base + c * kc (A_COMBINE) or y given (A_GIVEN).
+struct Pro {
+    int mode;
+    const double *y;   // A_GIVEN: y; A_COMBINE: base
+    const double *kc;  // may be null when c == 0
+    double c;
+    double *ywrite;    // A_COMBINE: y is written here when non-null
+};
+
+// Phase-C epilogue.
+struct Epi {
+    int mode;
+    const double *y;        // the stage's y (death term)
+    double *out;            // S is written here (k_i or dndt)
+    const double *n;        // current state (stage modes) or n0 (init modes)
+    const double *ks[SMOL_MAX_STAGE];
+    double coef[SMOL_MAX_STAGE];
+    int nks;                // previous stage vectors used
+    double cS;              // coefficient of this S
+    double h;
+    double *ynext;          // C_STAGE: next stage state
+    double rtol, atol;
+    double *epart;          // C_LAST / C_INIT*: [jobs][SMOL_EPART]
+};
+
+// Sum per-wave values sh[w][0..nq) over the waves in order (after a barrier).
+__device__ __forceinline__ double sum_waves(const double *sh, int nq, int q)
+{
+    double a = 0.0;
+#pragma unroll
+    for (int w = 0; w < SMOL_WAVES; ++w) a += sh[w * nq + q];
+    return a;
+}
+
+// --------------------------------------------------------------------------
+// Phase A
+// --------------------------------------------------------------------------
+
+template <int N1, int N2>
+struct PhaseA {
+    using F = FftShape<N1>;
+    static constexpr int COLS = (F::B < N2) ? F::B : N2;             // per wave
+    static constexpr int GA = (SMOL_WAVES * COLS < N2) ? SMOL_WAVES * COLS : N2;  // per unit
+    static constexpr int WUSED = GA / COLS;
+    static constexpr int NG = N2 / GA;                                // column groups
+    static constexpr int LDS = SMOL_WAVES * 64 * F::E;                // entries
+    static __host__ __device__ int units(int R) { return R * NG; }
+    static __host__ __device__ int red_jobs() { return NG; }
+
+    // one unit = (rank al, group of GA columns); whole workgroup
+    __device__ static void run(const RhsPlanDev &P, const Pro &in, int unit, cd *lds)
+    {
+        __shared__ double sh[SMOL_WAVES * 4];
+        const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
+        const int f = lane / F::G, g = lane % F::G;
+        const int al = unit / NG, grp = unit % NG;
+        const int n2 = grp * GA + w * COLS + f;
+        const bool active = (w < WUSED) && (f < COLS);
+        const int64_t M = P.M;
+        const double *Ua = P.U + (int64_t)al * P.ustride, *Va = P.V + (int64_t)al * P.ustride;
+        FftTw<N1, false> tw;
+        cd t4[F::E];
+        if (active) {
+            tw.load(g, P.rt);
+            step_twiddles<F::E, false>(P.rt, P.logL, (uint32_t)n2, g, F::G, t4);
+        }
+        cd v[F::E];
+        double sw = 0, st = 0, sr = 0, sp = 0;
+        const bool comb = in.mode == A_COMBINE;
+#pragma unroll
+        for (int i = 0; i < F::E; ++i) {
+            v[i] = cmk(0.0, 0.0);
+            if (i < F::E / 2 && active) {
+                const int64_t idx = (int64_t)(g + i * F::G) * N2 + n2;
+                if (idx < M) {
+                    const int64_t q = pos_of(P, idx);
+                    double yv = in.y[q];
+                    if (comb) {
+                        if (in.kc) yv = fma(in.c, in.kc[q], yv);
+                        if (in.ywrite && al == 0) in.ywrite[q] = yv;
+                    }
+                    const double u = Ua[q] * yv, x = Va[q] * yv;
+                    if (idx < M - 1) v[i] = cmk(u, x);
+                    if (comb) {
+                        const double s = (double)(idx + 1);
+                        sw += x;
+                        if (idx >= 1) {
+                            st = fma(s, x, st);
+                            sr += u;
+                            sp = fma(s, u, sp);
+                        }
+                    }
+                }
+            }
+        }
+        // When L = 2M - 2 the largest size sits at index L/2 (row N1/2 of
+        // column 0): not an FFT input, but part of y and of the reductions.
+        if (comb && active && n2 == 0 && g == 0 && (int64_t)(N1 / 2) * N2 < M) {
+            const int64_t idx = (int64_t)(N1 / 2) * N2;
+            const int64_t q = pos_of(P, idx);
+            double yv = in.y[q];
+            if (in.kc) yv = fma(in.c, in.kc[q], yv);
+            if (in.ywrite && al == 0) in.ywrite[q] = yv;
+            const double s = (double)(idx + 1);
+            const double u = Ua[q] * yv, x = Va[q] * yv;
+            sw += x;
+            st = fma(s, x, st);
+            sr += u;
+            sp = fma(s, u, sp);
+        }
+        cd *wl = lds + w * 64 * F::E;
+        if (active) {
+            wave_fft<N1, false>(v, wl + f * N1, g, tw);
+            wave_sync();
+#pragma unroll
+            for (int i = 0; i < F::E; ++i) wl[f * N1 + g + i * F::G] = cmul(v[i], t4[i]);
+        }
+        __syncthreads();
+        // store rows of GA consecutive columns
+        cd *Za = P.Z + ((int64_t)al << P.logL) + grp * GA;
+        for (int e = tid; e < GA * N1; e += SMOL_WG) {
+            const int c = e % GA, k1 = e / GA;
+            Za[(int64_t)k1 * N2 + c] = lds[(c / COLS) * 64 * F::E + (c % COLS) * N1 + k1];
+        }
+        if (comb) {
+            sw = wave_sum(sw);
+            st = wave_sum(st);
+            sr = wave_sum(sr);
+            sp = wave_sum(sp);
+            if (lane == 0) {
+                sh[w * 4 + 0] = sw;
+                sh[w * 4 + 1] = st;
+                sh[w * 4 + 2] = sr;
+                sh[w * 4 + 3] = sp;
+            }
+            __syncthreads();
+            if (tid < 4) P.red_part[((int64_t)grp * P.R + al) * 4 + tid] = sum_waves(sh, 4, tid);
+        }
+    }
+};
+
+// --------------------------------------------------------------------------
+// Phase B
+// --------------------------------------------------------------------------
+
+template <int N1, int N2>
+struct PhaseB {
+    using F = FftShape<N2>;
+    static constexpr int SLOTS = SMOL_WAVES * F::B;  // row transforms per round
+    static constexpr int AL_PER_ROUND = SLOTS / 2;   // ranks per round (2 rows each)
+    static __host__ __device__ int units() { return N1 / 2 + 1; }
+    // LDS entries: SLOTS rows + P for the two rows
+    static constexpr int LDS = SLOTS * N2 + 2 * N2;
+
+    // unit k1 in [0, N1/2]; whole workgroup
+    __device__ static void run(const RhsPlanDev &P, int k1, cd *lds)
+    {
+        const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+        const int f = lane / F::G, g = lane % F::G;
+        const int slot = wave * F::B + f;
+        const int k1p = (N1 - k1) & (N1 - 1);
+        const bool single = (k1 == k1p);  // k1 = 0 or N1/2
+        cd *rows = lds;
+        cd *P1 = lds + SLOTS * N2, *P2 = P1 + N2;
+        FftTw<N2, false> twf;
+        twf.load(g, P.rt);
+        for (int k2 = tid; k2 < N2; k2 += SMOL_WG) P1[k2] = cmk(0.0, 0.0);
+        for (int a0 = 0; a0 < P.R; a0 += AL_PER_ROUND) {
+            const int na = min(AL_PER_ROUND, P.R - a0);
+            // slot 2m holds rank a0+m row k1, slot 2m+1 its row N1-k1
+            {
+                const int m = slot >> 1, which = slot & 1;
+                if (m < na && !(single && which)) {
+                    const int krow = which ? k1p : k1;
+                    const cd *src = P.Z + ((int64_t)(a0 + m) << P.logL) + (int64_t)krow * N2;
+                    cd v[F::E];
+#pragma unroll
+                    for (int i = 0; i < F::E; ++i) v[i] = src[g + i * F::G];
+                    wave_fft<N2, false>(v, rows + slot * N2, g, twf);
+                    wave_sync();
+#pragma unroll
+                    for (int i = 0; i < F::E; ++i) rows[slot * N2 + g + i * F::G] = v[i];
+                }
+            }
+            __syncthreads();
+            for (int k2 = tid; k2 < N2; k2 += SMOL_WG) {
+                // partner of (k1, k2) is (k1p, k2p)
+                const int k2p = (k1 == 0) ? ((N2 - k2) & (N2 - 1)) : (N2 - 1 - k2);
+                cd acc = P1[k2];
+                for (int m = 0; m < na; ++m) {
+                    const cd a = rows[(2 * m) * N2 + k2];
+                    const cd b = rows[(2 * m + (single ? 0 : 1)) * N2 + k2p];
+                    // a^2 - conj(b)^2
+                    const double re = (a.x * a.x - a.y * a.y) - (b.x * b.x - b.y * b.y);
+                    const double im = 2.0 * (a.x * a.y + b.x * b.y);
+                    acc.x += re;
+                    acc.y += im;
+                }
+                P1[k2] = acc;
+            }
+            __syncthreads();
+        }
+        // divide by 4i: x / (4i) = (x.y, -x.x) / 4; partner row by conjugate reversal
+        for (int k2 = tid; k2 < N2; k2 += SMOL_WG) {
+            const cd x = P1[k2];
+            const cd q = cmk(0.25 * x.y, -0.25 * x.x);
+            P1[k2] = q;
+            if (!single) P2[N2 - 1 - k2] = cconj(q);
+        }
+        __syncthreads();
+        // inverse DFT over k2 of rows k1 (slot 0) and N1-k1 (slot 1)
+        if (slot < (single ? 1 : 2)) {
+            const int krow = slot ? k1p : k1;
+            FftTw<N2, true> twi;
+            twi.load(g, P.rt);
+            cd t4[F::E];
+            step_twiddles<F::E, true>(P.rt, P.logL, (uint32_t)krow, g, F::G, t4);
+            const cd *src = slot ? P2 : P1;
+            cd v[F::E];
+#pragma unroll
+            for (int i = 0; i < F::E; ++i) v[i] = src[g + i * F::G];
+            wave_fft<N2, true>(v, rows + slot * N2, g, twi);
+            cd *dst = P.Qp + (int64_t)krow * (N2 / 2);
+#pragma unroll
+            for (int i = 0; i < F::E / 2; ++i) {
+                const cd lo = cmul(v[i], t4[i]);
+                const cd hi = cmul(v[i + F::E / 2], t4[i + F::E / 2]);
+                dst[g + i * F::G] = cmk(lo.x - hi.y, lo.y + hi.x);  // lo + i*hi
+            }
+        }
+    }
+};
+
+// Sum reduction partials [njobs][R][4] in a fixed order into red[R][4]
+// (threads take fixed stripes of jobs, then the stripes are added in order).
+__device__ inline void finalize_reductions(const RhsPlanDev &P, int njobs)
+{
+    __shared__ double sh[SMOL_WG];
+    const int tid = threadIdx.x, nq = 4 * P.R, ns = SMOL_WG / nq;
+    const int q = tid % nq, s = tid / nq;
+    double acc = 0.0;
+    if (s < ns)
+        for (int j = s; j < njobs; j += ns) acc += P.red_part[(int64_t)j * nq + q];
+    sh[tid] = acc;
+    __syncthreads();
+    if (tid < nq) {
+        double tot = 0.0;
+        for (int k = 0; k < ns; ++k) tot += sh[k * nq + tid];
+        P.red[tid] = tot;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Phase C
+// --------------------------------------------------------------------------
+
+template <int N1, int N2>
+struct PhaseC {
+    using F = FftShape<N1>;
+    static constexpr int HALF = N2 / 2;
+    static constexpr int COLS = (F::B < HALF) ? F::B : HALF;  // packed columns per unit
+    static constexpr int NPOS = COLS * N1;                     // outputs per unit
+    static constexpr int PP = (NPOS + SMOL_WG - 1) / SMOL_WG;  // per thread
+    static constexpr int LDS = 64 * F::E;                      // wave 0 scratch
+    static __host__ __device__ int units() { return HALF / COLS; }
+    static __host__ __device__ int jobs() { return units(); }
+
+    __device__ static void run(const RhsPlanDev &P, const Epi &ep, int unit, cd *lds)
+    {
+        __shared__ double sh[SMOL_WAVES * SMOL_EPART];
+        const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
+        const int64_t M = P.M;
+        const int R = P.R;
+        const double lam = P.lam;
+        if (w == 0) {
+            const int f = lane / F::G, g = lane % F::G;
+            const int ac = unit * COLS + f;
+            FftTw<N1, true> tw;
+            tw.load(g, P.rt);
+            cd v[F::E];
+#pragma unroll
+            for (int i = 0; i < F::E; ++i)
+                v[i] = f < COLS ? P.Qp[(int64_t)(g + i * F::G) * HALF + ac] : cmk(0.0, 0.0);
+            wave_fft<N1, true>(v, lds + f * N1, g, tw);
+            wave_sync();
+            if (f < COLS) {
+#pragma unroll
+                for (int i = 0; i < F::E / 2; ++i) lds[f * (N1 / 2) + g + i * F::G] = v[i];
+            }
+        }
+        __syncthreads();
+        const double invL = 1.0 / (double)(1LL << P.logL);
+        double acc[SMOL_EPART];
+#pragma unroll
+        for (int q = 0; q < SMOL_EPART; ++q) acc[q] = 0.0;
+        int64_t posv[PP + 1], sizev[PP + 1];
+        int np = 0;
+#pragma unroll
+        for (int j = 0; j < PP; ++j) {
+            const int e = tid + j * SMOL_WG;
+            posv[j] = -1;
+            if (e < NPOS) {
+                const int b = e % (N1 / 2), hh = (e / (N1 / 2)) & 1, f = e / N1;
+                const int64_t m = unit * COLS + f + hh * HALF + (int64_t)N2 * b;
+                if (m <= M - 2) {
+                    const cd val = lds[f * (N1 / 2) + b];
+                    const double c = (hh ? val.y : val.x) * invL;
+                    const int64_t idx = m + 1;
+                    const int64_t q = pos_of(P, idx);
+                    double dsum = 0.0;
+                    for (int al = 0; al < R; ++al)
+                        dsum = fma(P.U[(int64_t)al * P.ustride + q], P.red[4 * al], dsum);
+                    const double S = fma(-(1.0 + lam) * ep.y[q], dsum, 0.5 * c);
+                    epilogue(ep, q, (double)(idx + 1), S, acc);
+                    posv[j] = q;
+                    sizev[j] = idx + 1;
+                    ++np;
+                }
+            }
+        }
+        // size 1 (index 0): monomer balance with the shattering gains
+        posv[PP] = -1;
+        if (unit == 0 && tid == 0) {
+            const double y1 = ep.y[0];
+            double d1 = 0.0, g1 = 0.0, pairs = 0.0;
+            for (int al = 0; al < R; ++al) {
+                const double wv = P.red[4 * al], t = P.red[4 * al + 1];
+                const double r = P.red[4 * al + 2], pp = P.red[4 * al + 3];
+                const double u1 = P.U[(int64_t)al * P.ustride];
+                const double q = wv - P.V[(int64_t)al * P.ustride] * y1;
+                d1 = fma(u1, wv, d1);
+                g1 = fma(u1, t, g1);
+                pairs = fma(pp, q, fma(r, t, pairs));
+            }
+            const double S1 = -y1 * d1 + 0.5 * lam * pairs + lam * y1 * g1;
+            epilogue(ep, 0, 1.0, S1, acc);
+            posv[PP] = 0;
+            sizev[PP] = 1;
+        }
+        (void)np;
+        if (ep.mode == C_STAGE) {
+            // reductions of the next stage state, rank by rank
+            for (int al = 0; al < R; ++al) {
+                double s4[4] = {0.0, 0.0, 0.0, 0.0};
+                const double *Ua = P.U + (int64_t)al * P.ustride, *Va = P.V + (int64_t)al * P.ustride;
+#pragma unroll
+                for (int j = 0; j <= PP; ++j) {
+                    const int64_t q = posv[j];
+                    if (q >= 0) {
+                        const double yn = ep.ynext[q];
+                        const double x = Va[q] * yn;
+                        s4[0] += x;
+                        if (sizev[j] >= 2) {
+                            const double sz = (double)sizev[j], u = Ua[q] * yn;
+                            s4[1] = fma(sz, x, s4[1]);
+                            s4[2] += u;
+                            s4[3] = fma(sz, u, s4[3]);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) s4[k] = wave_sum(s4[k]);
+                if (lane == 0)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) sh[w * 4 + k] = s4[k];
+                __syncthreads();
+                if (tid < 4) P.red_part[((int64_t)unit * R + al) * 4 + tid] = sum_waves(sh, 4, tid);
+                __syncthreads();
+            }
+        } else if (ep.mode != C_RHS) {
+#pragma unroll
+            for (int q = 0; q < SMOL_EPART; ++q) acc[q] = wave_sum(acc[q]);
+            if (lane == 0)
+#pragma unroll
+                for (int q = 0; q < SMOL_EPART; ++q) sh[w * SMOL_EPART + q] = acc[q];
+            __syncthreads();
+            if (tid < SMOL_EPART)
+                ep.epart[(int64_t)unit * SMOL_EPART + tid] = sum_waves(sh, SMOL_EPART, tid);
+        }
+    }
+
+    // per-element epilogue at position q (size s); accumulates partials
+    __device__ static void epilogue(const Epi &ep, int64_t q, double s, double S, double *acc)
+    {
+        switch (ep.mode) {
+        case C_RHS:
+            ep.out[q] = S;
+            break;
+        case C_STAGE: {
+            ep.out[q] = S;
+            double a = ep.cS * S;
+            for (int j = 0; j < ep.nks; ++j) a = fma(ep.coef[j], ep.ks[j][q], a);
+            ep.ynext[q] = fma(ep.h, a, ep.n[q]);
+            break;
+        }
+        case C_LAST: {
+            ep.out[q] = S;
+            double e = ep.cS * S;
+            for (int j = 0; j < ep.nks; ++j) e = fma(ep.coef[j], ep.ks[j][q], e);
+            e *= ep.h;
+            const double yn = ep.y[q], y0 = ep.n[q];
+            const double sc = fma(ep.rtol, fmax(fabs(y0), fabs(yn)), ep.atol);
+            const double r = e / sc;
+            acc[0] = fma(r, r, acc[0]);
+            acc[1] += yn;
+            acc[2] = fma(s, yn, acc[2]);
+            acc[3] = fma(s * s, yn, acc[3]);
+            acc[4] = fma(s * s * s, yn, acc[4]);
+            if (!isfinite(yn)) acc[5] += 1.0;
+            break;
+        }
+        case C_INIT0: {
+            ep.out[q] = S;
+            const double y0 = ep.n[q];
+            const double sc = fma(ep.rtol, fabs(y0), ep.atol);
+            const double a = y0 / sc, b = S / sc;
+            acc[0] = fma(a, a, acc[0]);
+            acc[1] = fma(b, b, acc[1]);
+            if (!isfinite(y0)) acc[5] += 1.0;
+            break;
+        }
+        default: {  // C_INIT1
+            const double y0 = ep.n[q];
+            const double sc = fma(ep.rtol, fabs(y0), ep.atol);
+            const double d = (S - ep.ks[0][q]) / sc;
+            acc[0] = fma(d, d, acc[0]);
+            break;
+        }
+        }
+    }
+};

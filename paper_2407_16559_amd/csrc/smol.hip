@@ -1,0 +1,853 @@
+// libsmol: C ABI, plans and kernel launches (gfx950).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "../../include/smol.h"
+#include "integrate.h"
+
+#define SMOL_VERSION "0.1.0"
+
+// --------------------------------------------------------------------------
+// Kernels (multi-launch form of the three phases)
+// --------------------------------------------------------------------------
+
+// Map workgroup b to a logical index so that consecutive logical indices land
+// on the same XCD (workgroups are dealt round-robin over the 8 XCDs).
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    if (nb % 8) return b;
+    return (b % 8) * (nb / 8) + b / 8;
+}
+
+template <int N1, int N2>
+__global__ __launch_bounds__(SMOL_WG) void k_phaseA(RhsPlanDev P, Pro in, int nunits)
+{
+    extern __shared__ cd lds[];
+    const int unit = xcd_remap(blockIdx.x, gridDim.x);
+    if (unit < nunits) PhaseA<N1, N2>::run(P, in, unit, lds);
+}
+
+template <int N1, int N2>
+__global__ __launch_bounds__(SMOL_WG) void k_phaseB(RhsPlanDev P, int red_jobs)
+{
+    extern __shared__ cd lds[];
+    const int u = blockIdx.x;
+    if (u == PhaseB<N1, N2>::units()) {
+        if (red_jobs > 0) finalize_reductions(P, red_jobs);
+        return;
+    }
+    PhaseB<N1, N2>::run(P, u, lds);
+}
+
+template <int N1, int N2>
+__global__ __launch_bounds__(SMOL_WG) void k_phaseC(RhsPlanDev P, Epi ep, int nunits)
+{
+    extern __shared__ cd lds[];
+    const int unit = xcd_remap(blockIdx.x, gridDim.x);
+    if (unit < nunits) PhaseC<N1, N2>::run(P, ep, unit, lds);
+}
+
+// Layout conversion of `rows` vectors of M sizes: natural <-> transposed.
+__global__ void k_to_tr(const double *src, double *dst, int64_t M, int rows, int64_t sstride,
+                        int64_t dstride, int logL)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < M * rows;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / M, idx = i % M;
+        dst[r * dstride + pos_tr(idx, logL)] = src[r * sstride + idx];
+    }
+}
+__global__ void k_from_tr(const double *src, double *dst, int64_t M, int logL)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < M;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[pos_tr(i, logL)];
+}
+
+
+// --------------------------------------------------------------------------
+// Integration kernels: the same phases, buffers chosen from the control block
+// --------------------------------------------------------------------------
+
+template <int N1, int N2>
+__global__ __launch_bounds__(SMOL_WG) void k_int_A(IntegDev I, int stage, int nunits)
+{
+    const IntegCtl &c = *I.ctl;
+    if (c.done) return;
+    extern __shared__ cd lds[];
+    const Tableau &T = c_tab[c.method];
+    const RhsPlanDev P = plan_of(I, c);
+    const Pro in = stage_pro(I, c, T, stage);
+    const int unit = xcd_remap(blockIdx.x, gridDim.x);
+    if (unit < nunits) PhaseA<N1, N2>::run(P, in, unit, lds);
+}
+
+template <int N1, int N2>
+__global__ __launch_bounds__(SMOL_WG) void k_int_B(IntegDev I, int stage)
+{
+    const IntegCtl &c = *I.ctl;
+    if (c.done) return;
+    extern __shared__ cd lds[];
+    const RhsPlanDev P = plan_of(I, c);
+    const int u = blockIdx.x;
+    if (u == PhaseB<N1, N2>::units()) {
+        // partials of y come from phase A (stages 0..2) or the previous finish
+        finalize_reductions(P, stage <= 2 ? PhaseA<N1, N2>::red_jobs() : PhaseC<N1, N2>::units());
+        return;
+    }
+    PhaseB<N1, N2>::run(P, u, lds);
+}
+
+template <int N1, int N2>
+__global__ __launch_bounds__(SMOL_WG) void k_int_C(IntegDev I, int stage, int nunits)
+{
+    const IntegCtl &c = *I.ctl;
+    if (c.done) return;
+    extern __shared__ cd lds[];
+    const Tableau &T = c_tab[c.method];
+    const RhsPlanDev P = plan_of(I, c);
+    const Epi ep = stage_epi(I, c, T, stage);
+    const int unit = xcd_remap(blockIdx.x, gridDim.x);
+    if (unit < nunits) PhaseC<N1, N2>::run(P, ep, unit, lds);
+}
+
+// Deterministic block reduction of epart rows (fixed strided order, then a
+// fixed tree); thread 0 receives the totals.
+__device__ inline void block_sum_epart(const double *ep, int njobs, double *tot)
+{
+    __shared__ double sh[SMOL_WG][SMOL_EPART];
+    const int tid = threadIdx.x;
+    double acc[SMOL_EPART];
+    for (int q = 0; q < SMOL_EPART; ++q) acc[q] = 0.0;
+    for (int j = tid; j < njobs; j += SMOL_WG)
+        for (int q = 0; q < SMOL_EPART; ++q) acc[q] += ep[(int64_t)j * SMOL_EPART + q];
+    for (int q = 0; q < SMOL_EPART; ++q) sh[tid][q] = acc[q];
+    __syncthreads();
+    for (int off = SMOL_WG / 2; off >= 1; off >>= 1) {
+        if (tid < off)
+            for (int q = 0; q < SMOL_EPART; ++q) sh[tid][q] += sh[tid + off][q];
+        __syncthreads();
+    }
+    if (tid == 0)
+        for (int q = 0; q < SMOL_EPART; ++q) tot[q] = sh[0][q];
+}
+
+__device__ __forceinline__ double rms_of(double sumsq, int64_t M) { return sqrt(sumsq / (double)M); }
+
+// Starting step, first half: d0, d1 from S(n0); h0.  With a user h0 the
+// first attempt is prepared right away.
+__global__ __launch_bounds__(SMOL_WG) void k_init_h0(IntegDev I, int njobs)
+{
+    IntegCtl &c = *I.ctl;
+    if (c.done) return;
+    double tot[SMOL_EPART];
+    block_sum_epart(I.epart, njobs, tot);
+    if (threadIdx.x) return;
+    c.n_rhs = 1;
+    if (tot[5] > 0.0) {
+        c.status = ST_ENONFINITE;
+        c.done = 1;
+        c.n_rhs = 0;
+        return;
+    }
+    const double d0 = rms_of(tot[0], I.M), d1 = rms_of(tot[1], I.M);
+    double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+    if (h0 > c.t_end) h0 = c.t_end;
+    c.h0 = h0;
+    c.err = d1;  // kept for the second half
+    if (c.h0_user > 0.0) {
+        c.h = c.h0_user > c.t_end ? c.t_end : c.h0_user;
+        prepare_attempt(c, true);
+    }
+}
+
+// Starting step, second half (Hairer, Norsett & Wanner I, Sec. II.4).
+__global__ __launch_bounds__(SMOL_WG) void k_init_h(IntegDev I, int njobs)
+{
+    IntegCtl &c = *I.ctl;
+    if (c.done) return;
+    double tot[SMOL_EPART];
+    block_sum_epart(I.epart, njobs, tot);
+    if (threadIdx.x) return;
+    const Tableau &T = c_tab[c.method];
+    c.n_rhs = 2;
+    const double d1 = c.err, h0 = c.h0;
+    const double d2 = rms_of(tot[0], I.M) / h0;
+    double h1;
+    if (d1 <= 1e-15 && d2 <= 1e-15)
+        h1 = fmax(1e-6, h0 * 1e-3);
+    else
+        h1 = pow(0.01 / fmax(d1, d2), 1.0 / (double)(T.q + 1));
+    double h = 100.0 * h0;
+    if (h1 < h) h = h1;
+    if (c.t_end < h) h = c.t_end;
+    c.h = h;
+    c.err = 0.0;
+    prepare_attempt(c, true);
+}
+
+// Accept / reject and the next step size (PI controller), after the last stage.
+__global__ __launch_bounds__(SMOL_WG) void k_ctrl(IntegDev I, int njobs)
+{
+    IntegCtl &c = *I.ctl;
+    if (c.done) return;
+    double tot[SMOL_EPART];
+    block_sum_epart(I.epart, njobs, tot);
+    if (threadIdx.x) return;
+    const Tableau &T = c_tab[c.method];
+    const int k = T.q + 1;
+    const double err = rms_of(tot[0], I.M);
+    c.err = err;
+    c.attempts += 1;
+    c.n_rhs += T.S - 1;
+    const bool accept = err <= 1.0;
+    if (c.log && c.attempts <= c.log_cap) {
+        double *row = c.log + (c.attempts - 1) * 9;
+        row[0] = c.t;
+        row[1] = c.h;
+        row[2] = err;
+        row[3] = accept ? 1.0 : 0.0;
+        row[4] = accept ? c.t_new : c.t;
+        row[5] = tot[1];
+        row[6] = tot[2];
+        row[7] = tot[3];
+        row[8] = tot[4];
+    }
+    // a NaN norm or a non-finite new state ends the run (state kept)
+    if (isnan(err) || tot[5] > 0.0) {
+        c.status = ST_ENONFINITE;
+        c.done = 1;
+        return;
+    }
+    if (accept) {
+        double fac;
+        if (err == 0.0)
+            fac = c.facmax;
+        else
+            fac = c.safety * pow(err, -c.alpha) * pow(c.err_prev, c.beta);
+        if (fac > c.facmax) fac = c.facmax;
+        if (fac < c.facmin) fac = c.facmin;
+        if (c.rejected && fac > 1.0) fac = 1.0;
+        c.err_prev = fmax(err, 1e-4);
+        c.t = c.t_new;
+        c.h = c.h * fac;
+        c.cur ^= 1;
+        c.kp ^= 1;
+        c.n_accept += 1;
+        c.rejected = 0;
+        if (c.t >= c.t_end) {
+            c.status = ST_OK;
+            c.done = 1;
+            return;
+        }
+        prepare_attempt(c, true);
+    } else {
+        double fac = c.safety * pow(err, -1.0 / (double)k);
+        if (fac < c.facmin) fac = c.facmin;
+        c.h = c.h * fac;
+        c.rejected = 1;
+        c.n_reject += 1;
+        prepare_attempt(c, false);
+    }
+}
+
+// --------------------------------------------------------------------------
+// Host side
+// --------------------------------------------------------------------------
+
+namespace {
+
+int hip_fail(hipError_t e, const char *what)
+{
+    if (getenv("SMOL_DEBUG")) fprintf(stderr, "libsmol: %s: %s\n", what, hipGetErrorString(e));
+    return SMOL_EDEVICE;
+}
+#define HIP_TRY(x)                                   \
+    do {                                             \
+        hipError_t e_ = (x);                         \
+        if (e_ != hipSuccess) return hip_fail(e_, #x); \
+    } while (0)
+
+struct DevRoots {
+    cd *tw = nullptr, *fine = nullptr;
+};
+
+struct Plan {
+    int dev = -1;
+    int64_t M = 0;
+    int R = 0, precision = 0;
+    int logL = 0, logN1 = 0, logN2 = 0;
+    cd *Z = nullptr, *Qp = nullptr;
+    double *red_part = nullptr, *red = nullptr, *epart = nullptr;
+    // integration state (allocated on first use)
+    int64_t Mt = 0;                // vector length in the transposed layout
+    double *ibuf = nullptr;        // nb[2], kslot[7], ybuf: 10 Mt doubles
+    double *uvt = nullptr;         // transposed U and V: 2 R Mt doubles
+    IntegCtl *ctl = nullptr;       // device control block
+    IntegCtl *host = nullptr;      // pinned mirror
+    hipStream_t cap = nullptr;     // capture stream
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+};
+
+std::mutex g_mu;
+std::map<int, DevRoots> g_roots;
+std::map<std::tuple<int, int64_t, int, int>, Plan *> g_plans;
+
+int ilog2_ceil(int64_t x)
+{
+    int l = 0;
+    while ((1LL << l) < x) ++l;
+    return l;
+}
+
+int get_roots(int dev, DevRoots **out)
+{
+    auto it = g_roots.find(dev);
+    if (it != g_roots.end()) {
+        *out = &it->second;
+        return SMOL_OK;
+    }
+    std::vector<cd> host(2 * SMOL_TW);
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    for (int e = 0; e < SMOL_TW; ++e) {
+        long double a = two_pi * (long double)e / (long double)SMOL_TW;
+        host[e] = cd{(double)cosl(a), (double)-sinl(a)};
+        long double b = two_pi * (long double)e / (long double)(1 << SMOL_LOG_LMAX);
+        host[SMOL_TW + e] = cd{(double)cosl(b), (double)-sinl(b)};
+    }
+    DevRoots r;
+    HIP_TRY(hipMalloc(&r.tw, sizeof(cd) * 2 * SMOL_TW));
+    r.fine = r.tw + SMOL_TW;
+    HIP_TRY(hipMemcpy(r.tw, host.data(), sizeof(cd) * 2 * SMOL_TW, hipMemcpyHostToDevice));
+    g_roots[dev] = r;
+    *out = &g_roots[dev];
+    return SMOL_OK;
+}
+
+void free_plan(Plan *p)
+{
+    if (!p) return;
+    (void)hipFree(p->Z);  // Qp lives in the same allocation
+    (void)hipFree(p->red_part);
+    for (auto &g : p->graph)
+        if (g) (void)hipGraphExecDestroy(g);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    (void)hipFree(p->ibuf);
+    (void)hipFree(p->uvt);
+    (void)hipFree(p->ctl);
+    if (p->host) (void)hipHostFree(p->host);
+    delete p;
+}
+
+int get_plan(int64_t M, int R, int precision, Plan **out)
+{
+    int dev;
+    HIP_TRY(hipGetDevice(&dev));
+    auto key = std::make_tuple(dev, M, R, precision);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) {
+        *out = it->second;
+        return SMOL_OK;
+    }
+    Plan *p = new Plan();
+    p->dev = dev;
+    p->M = M;
+    p->R = R;
+    p->precision = precision;
+    int logL = ilog2_ceil(2 * M - 2);
+    if (logL < 6) logL = 6;
+    p->logL = logL;
+    p->logN1 = (logL + 1) / 2;
+    p->logN2 = logL / 2;
+    const int64_t L = 1LL << logL;
+    const int64_t N2 = 1LL << p->logN2;
+    hipError_t e = hipMalloc(&p->Z, sizeof(cd) * (size_t)(R * L + L / 2));
+    if (e != hipSuccess) {
+        delete p;
+        return SMOL_ENOMEM;
+    }
+    p->Qp = p->Z + R * L;
+    const size_t nred = (size_t)N2 * R * 4 + (size_t)R * 4 + (size_t)N2 * SMOL_EPART;
+    e = hipMalloc(&p->red_part, sizeof(double) * nred);
+    if (e != hipSuccess) {
+        (void)hipFree(p->Z);
+        delete p;
+        return SMOL_ENOMEM;
+    }
+    p->red = p->red_part + (size_t)N2 * R * 4;
+    p->epart = p->red + (size_t)R * 4;
+    g_plans[key] = p;
+    *out = p;
+    return SMOL_OK;
+}
+
+RhsPlanDev dev_plan(const Plan *p, const DevRoots *r, const double *U, const double *V, double lam)
+{
+    RhsPlanDev d;
+    d.M = p->M;
+    d.R = p->R;
+    d.logL = p->logL;
+    d.logN1 = p->logN1;
+    d.logN2 = p->logN2;
+    d.tr = 0;
+    d.ustride = p->M;
+    d.lam = lam;
+    d.U = U;
+    d.V = V;
+    d.Z = p->Z;
+    d.Qp = p->Qp;
+    d.red_part = p->red_part;
+    d.red = p->red;
+    d.rt.tw = r->tw;
+    d.rt.fine = r->fine;
+    return d;
+}
+
+// Launch phases A, B, C for one right-hand side.
+template <int N1, int N2>
+int launch_rhs_t(const RhsPlanDev &P, const Pro &in, const Epi &ep, hipStream_t s)
+{
+    using A = PhaseA<N1, N2>;
+    using B = PhaseB<N1, N2>;
+    using C = PhaseC<N1, N2>;
+    const int nA = A::units(P.R), nC = C::units();
+    hipLaunchKernelGGL((k_phaseA<N1, N2>), dim3(nA), dim3(SMOL_WG), sizeof(cd) * A::LDS, s, P,
+                       in, nA);
+    const int redj = (in.mode == A_COMBINE) ? A::red_jobs() : 0;
+    hipLaunchKernelGGL((k_phaseB<N1, N2>), dim3(B::units() + 1), dim3(SMOL_WG),
+                       sizeof(cd) * B::LDS, s, P, redj);
+    hipLaunchKernelGGL((k_phaseC<N1, N2>), dim3(nC), dim3(SMOL_WG), sizeof(cd) * C::LDS, s, P,
+                       ep, nC);
+    HIP_TRY(hipGetLastError());
+    return SMOL_OK;
+}
+
+int launch_rhs(const RhsPlanDev &P, const Pro &in, const Epi &ep, hipStream_t s)
+{
+    switch (P.logL) {
+#define CASE(LL, A, B) \
+    case LL: return launch_rhs_t<(1 << A), (1 << B)>(P, in, ep, s);
+        CASE(6, 3, 3)
+        CASE(7, 4, 3)
+        CASE(8, 4, 4)
+        CASE(9, 5, 4)
+        CASE(10, 5, 5)
+        CASE(11, 6, 5)
+        CASE(12, 6, 6)
+        CASE(13, 7, 6)
+        CASE(14, 7, 7)
+        CASE(15, 8, 7)
+        CASE(16, 8, 8)
+        CASE(17, 9, 8)
+        CASE(18, 9, 9)
+        CASE(19, 10, 9)
+        CASE(20, 10, 10)
+#undef CASE
+    default: return SMOL_EUNSUPPORTED;
+    }
+}
+
+// Call F::template run<N1, N2>(args...) for the plan's transform shape.
+template <class F, class... Args>
+int with_shape(int logL, Args &&...args)
+{
+    switch (logL) {
+#define CASE(LL, A, B) \
+    case LL: return F::template run<(1 << A), (1 << B)>(args...);
+        CASE(6, 3, 3)
+        CASE(7, 4, 3)
+        CASE(8, 4, 4)
+        CASE(9, 5, 4)
+        CASE(10, 5, 5)
+        CASE(11, 6, 5)
+        CASE(12, 6, 6)
+        CASE(13, 7, 6)
+        CASE(14, 7, 7)
+        CASE(15, 8, 7)
+        CASE(16, 8, 8)
+        CASE(17, 9, 8)
+        CASE(18, 9, 9)
+        CASE(19, 10, 9)
+        CASE(20, 10, 10)
+#undef CASE
+    default: return SMOL_EUNSUPPORTED;
+    }
+}
+
+// One stage (or starting-step evaluation) of the integrator: A, B, C.
+struct LaunchStage {
+    template <int N1, int N2>
+    static int run(const IntegDev &I, int stage, hipStream_t s)
+    {
+        using A = PhaseA<N1, N2>;
+        using B = PhaseB<N1, N2>;
+        using C = PhaseC<N1, N2>;
+        const int nA = A::units(I.R), nC = C::units();
+        hipLaunchKernelGGL((k_int_A<N1, N2>), dim3(nA), dim3(SMOL_WG), sizeof(cd) * A::LDS, s, I,
+                           stage, nA);
+        hipLaunchKernelGGL((k_int_B<N1, N2>), dim3(B::units() + 1), dim3(SMOL_WG),
+                           sizeof(cd) * B::LDS, s, I, stage);
+        hipLaunchKernelGGL((k_int_C<N1, N2>), dim3(nC), dim3(SMOL_WG), sizeof(cd) * C::LDS, s, I,
+                           stage, nC);
+        HIP_TRY(hipGetLastError());
+        return SMOL_OK;
+    }
+};
+
+struct PhaseCJobs {
+    template <int N1, int N2>
+    static int run()
+    {
+        return PhaseC<N1, N2>::units();
+    }
+};
+
+int alloc_integ(Plan *p)
+{
+    if (p->ibuf) return SMOL_OK;
+    const int64_t half = 1LL << (p->logL - 1);
+    p->Mt = p->M > half + 1 ? p->M : half + 1;
+    if (hipMalloc(&p->ibuf, sizeof(double) * (size_t)p->Mt * 10) != hipSuccess) return SMOL_ENOMEM;
+    if (hipMalloc(&p->uvt, sizeof(double) * (size_t)p->Mt * 2 * p->R) != hipSuccess) return SMOL_ENOMEM;
+    if (hipMalloc(&p->ctl, sizeof(IntegCtl)) != hipSuccess) return SMOL_ENOMEM;
+    HIP_TRY(hipHostMalloc(&p->host, sizeof(IntegCtl), hipHostMallocDefault));
+    HIP_TRY(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+    return SMOL_OK;
+}
+
+IntegDev integ_dev(const Plan *p, const DevRoots *r)
+{
+    IntegDev I{};
+    I.M = p->M;
+    I.R = p->R;
+    I.logL = p->logL;
+    I.ctl = p->ctl;
+    I.Mt = p->Mt;
+    I.Ut = p->uvt;
+    I.Vt = p->uvt + (size_t)p->R * p->Mt;
+    I.nb[0] = p->ibuf;
+    I.nb[1] = p->ibuf + p->Mt;
+    for (int j = 0; j < 7; ++j) I.kslot[j] = p->ibuf + (2 + j) * p->Mt;
+    I.kslot[7] = nullptr;
+    I.ybuf = p->ibuf + 9 * p->Mt;
+    I.Z = p->Z;
+    I.Qp = p->Qp;
+    I.red_part = p->red_part;
+    I.red = p->red;
+    I.epart = p->epart;
+    I.rt.tw = r->tw;
+    I.rt.fine = r->fine;
+    I.mlp = nullptr;
+    return I;
+}
+
+// Capture one step attempt (stages 2..S, controller) as a graph.
+int get_step_graph(Plan *p, const IntegDev &I, int method, hipGraphExec_t *out)
+{
+    if (p->graph[method]) {
+        *out = p->graph[method];
+        return SMOL_OK;
+    }
+    const int S = method == SMOL_DP54 ? 7 : 4;
+    const int nC = with_shape<PhaseCJobs>(p->logL);
+    hipGraph_t g;
+    HIP_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+    int rc = SMOL_OK;
+    for (int st = 2; st <= S && rc == SMOL_OK; ++st) rc = with_shape<LaunchStage>(p->logL, I, st, p->cap);
+    hipLaunchKernelGGL(k_ctrl, dim3(1), dim3(SMOL_WG), 0, p->cap, I, nC);
+    hipError_t e = hipStreamEndCapture(p->cap, &g);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&p->graph[method], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    *out = p->graph[method];
+    return SMOL_OK;
+}
+
+void stats_from(const IntegCtl &c, smol_stats *st)
+{
+    if (!st) return;
+    st->n_rhs = c.n_rhs;
+    st->n_accept = c.n_accept;
+    st->n_reject = c.n_reject;
+    st->t = c.t;
+    st->h = c.h;
+    st->err = c.err;
+    st->status = c.status;
+    st->n_fallback = c.n_fallback;
+}
+
+int check_common(int64_t M, int32_t R, const double *U, const double *V, double lambda)
+{
+    if (M < 1 || R < 1 || R > SMOL_MAX_R || !U || !V) return SMOL_EINVAL;
+    if (!std::isfinite(lambda) || lambda < 0) return SMOL_EINVAL;
+    if (2 * M - 2 > (1LL << SMOL_LOG_LMAX)) return SMOL_EUNSUPPORTED;
+    return SMOL_OK;
+}
+
+}  // namespace
+
+// --------------------------------------------------------------------------
+// C ABI
+// --------------------------------------------------------------------------
+
+extern "C" int smol_rhs(int64_t M, int32_t R, const double *U, const double *V, double lambda,
+                        const double *n, double *dndt, int32_t precision, void *stream)
+{
+    int rc = check_common(M, R, U, V, lambda);
+    if (rc) return rc;
+    if (!n || !dndt || n == dndt) return SMOL_EINVAL;
+    if (precision != SMOL_FP64 && precision != SMOL_FP32X2) return SMOL_EINVAL;
+    if (precision != SMOL_FP64) return SMOL_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Plan *p;
+    DevRoots *r;
+    if ((rc = get_plan(M, R, precision, &p))) return rc;
+    if ((rc = get_roots(p->dev, &r))) return rc;
+    RhsPlanDev P = dev_plan(p, r, U, V, lambda);
+    Pro in{A_COMBINE, n, nullptr, 0.0, nullptr};
+    Epi ep{};
+    ep.mode = C_RHS;
+    ep.y = n;
+    ep.out = dndt;
+    return launch_rhs(P, in, ep, (hipStream_t)stream);
+}
+
+extern "C" int smol_release_plans(void)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    int dev;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceSynchronize());
+    for (auto it = g_plans.begin(); it != g_plans.end();) {
+        if (std::get<0>(it->first) == dev) {
+            free_plan(it->second);
+            it = g_plans.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    return SMOL_OK;
+}
+
+extern "C" const char *smol_strerror(int code)
+{
+    switch (code) {
+    case SMOL_OK: return "ok";
+    case SMOL_EINVAL: return "invalid argument";
+    case SMOL_ENOMEM: return "device allocation failed";
+    case SMOL_EDEVICE: return "HIP runtime error";
+    case SMOL_ESTEPSIZE: return "step size fell below the minimum";
+    case SMOL_EMAXSTEPS: return "step-attempt limit reached";
+    case SMOL_ENONFINITE: return "non-finite state or error norm";
+    case SMOL_EUNSUPPORTED: return "unsupported request";
+    default: return "unknown status code";
+    }
+}
+
+extern "C" const char *smol_version(void) { return SMOL_VERSION; }
+
+
+extern "C" int smol_integrate_ex(int64_t M, int32_t R, const double *U, const double *V,
+                                 double lambda, const double *n0, double t_end, double rtol,
+                                 double atol, int32_t method, int32_t precision,
+                                 const smol_options *opts, double *n_out, smol_stats *stats,
+                                 void *stream)
+{
+    int rc = check_common(M, R, U, V, lambda);
+    if (rc) return rc;
+    if (!n0 || !n_out) return SMOL_EINVAL;
+    if (method != SMOL_BS32 && method != SMOL_DP54) return SMOL_EINVAL;
+    if (precision != SMOL_FP64 && precision != SMOL_FP32X2) return SMOL_EINVAL;
+    if (!(rtol > 0) || !(atol >= 0) || !(t_end >= 0) || !std::isfinite(t_end)) return SMOL_EINVAL;
+    smol_options o{};
+    if (opts) o = *opts;
+    if (o.h0 < 0 || o.h_min < 0 || o.max_steps < 0 || (o.log && o.log_cap < 0)) return SMOL_EINVAL;
+    if (o.controller != SMOL_CTRL_PI && o.controller != SMOL_CTRL_LEARNED) return SMOL_EINVAL;
+    if (precision != SMOL_FP64 || o.controller != SMOL_CTRL_PI) return SMOL_EUNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    if (stats) memset(stats, 0, sizeof(*stats));
+    if (t_end == 0.0) {
+        if (n_out != n0) HIP_TRY(hipMemcpyAsync(n_out, n0, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return SMOL_OK;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    Plan *p;
+    DevRoots *r;
+    if ((rc = get_plan(M, R, precision, &p))) return rc;
+    if ((rc = get_roots(p->dev, &r))) return rc;
+    if ((rc = alloc_integ(p))) return rc;
+    const IntegDev I = integ_dev(p, r);
+    const Tableau *Tdummy = nullptr;
+    (void)Tdummy;
+    const int k = (method == SMOL_DP54 ? 4 : 2) + 1;
+    IntegCtl &c = *p->host;
+    memset(&c, 0, sizeof(c));
+    c.U = I.Ut;
+    c.V = I.Vt;
+    c.lam = lambda;
+    c.t_end = t_end;
+    c.rtol = rtol;
+    c.atol = atol;
+    c.h_min = o.h_min;
+    c.h0_user = o.h0;
+    if (o.alpha > 0) {
+        c.alpha = o.alpha;
+        c.beta = o.beta;
+    } else {
+        c.alpha = 0.7 / k;
+        c.beta = 0.4 / k;
+    }
+    c.safety = 0.9;
+    c.facmin = 0.2;
+    c.facmax = 10.0;
+    c.max_steps = o.max_steps > 0 ? o.max_steps : 100000000LL;
+    c.log = o.log;
+    c.log_cap = o.log ? o.log_cap : 0;
+    c.method = method;
+    c.controller = o.controller;
+    c.err_prev = 1.0;
+    HIP_TRY(hipMemcpyAsync(p->ctl, &c, sizeof(c), hipMemcpyHostToDevice, s));
+    // the integrator keeps every vector in the transposed layout
+    hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, U, I.Ut, M, R, M, I.Mt, p->logL);
+    hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, V, I.Vt, M, R, M, I.Mt, p->logL);
+    hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, n0, I.nb[0], M, 1, M, I.Mt, p->logL);
+    const int nC = with_shape<PhaseCJobs>(p->logL);
+    // starting step: S(n0), h0, S(n0 + h0 f0), h
+    if ((rc = with_shape<LaunchStage>(p->logL, I, 0, s))) return rc;
+    hipLaunchKernelGGL(k_init_h0, dim3(1), dim3(SMOL_WG), 0, s, I, nC);
+    if (!(o.h0 > 0)) {
+        if ((rc = with_shape<LaunchStage>(p->logL, I, 1, s))) return rc;
+        hipLaunchKernelGGL(k_init_h, dim3(1), dim3(SMOL_WG), 0, s, I, nC);
+    }
+    HIP_TRY(hipGetLastError());
+    hipGraphExec_t ge;
+    if ((rc = get_step_graph(p, I, method, &ge))) return rc;
+    // replay step attempts; poll the control block between chunks
+    int64_t chunk = 4;
+    for (;;) {
+        for (int64_t i = 0; i < chunk; ++i) HIP_TRY(hipGraphLaunch(ge, s));
+        HIP_TRY(hipMemcpyAsync(p->host, p->ctl, sizeof(IntegCtl), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (c.done) break;
+        double est = (c.h > 0) ? (c.t_end - c.t) / c.h : 1e9;
+        if (!(est < 1e9)) est = 1e9;
+        chunk = (int64_t)(0.8 * est) + 1;
+        if (chunk > 256) chunk = 256;
+        if (chunk < 1) chunk = 1;
+    }
+    hipLaunchKernelGGL(k_from_tr, dim3(256), dim3(256), 0, s, I.nb[c.cur], n_out, M, p->logL);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    stats_from(c, stats);
+    return c.status;
+}
+
+extern "C" int smol_integrate(int64_t M, int32_t R, const double *U, const double *V,
+                              double lambda, const double *n0, double t_end, double rtol,
+                              double atol, int32_t method, int32_t precision, double *n_out,
+                              smol_stats *stats, void *stream)
+{
+    return smol_integrate_ex(M, R, U, V, lambda, n0, t_end, rtol, atol, method, precision,
+                             nullptr, n_out, stats, stream);
+}
+
+
+namespace {
+struct ProfileRhs {
+    template <int N1, int N2>
+    static int run(const RhsPlanDev &P, const Pro &in, const Epi &ep, int iters, float *ms,
+                   hipStream_t s)
+    {
+        using A = PhaseA<N1, N2>;
+        using B = PhaseB<N1, N2>;
+        using C = PhaseC<N1, N2>;
+        const int nA = A::units(P.R), nC = C::units();
+        hipEvent_t ev[5];
+        for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+        HIP_TRY(hipEventRecord(ev[0], s));
+        for (int i = 0; i < iters; ++i)
+            hipLaunchKernelGGL((k_phaseA<N1, N2>), dim3(nA), dim3(SMOL_WG), sizeof(cd) * A::LDS, s,
+                               P, in, nA);
+        HIP_TRY(hipEventRecord(ev[1], s));
+        for (int i = 0; i < iters; ++i)
+            hipLaunchKernelGGL((k_phaseB<N1, N2>), dim3(B::units() + 1), dim3(SMOL_WG),
+                               sizeof(cd) * B::LDS, s, P, A::red_jobs());
+        HIP_TRY(hipEventRecord(ev[2], s));
+        for (int i = 0; i < iters; ++i)
+            hipLaunchKernelGGL((k_phaseC<N1, N2>), dim3(nC), dim3(SMOL_WG), sizeof(cd) * C::LDS, s,
+                               P, ep, nC);
+        HIP_TRY(hipEventRecord(ev[3], s));
+        for (int i = 0; i < iters; ++i) {
+            int rc = launch_rhs_t<N1, N2>(P, in, ep, s);
+            if (rc) return rc;
+        }
+        HIP_TRY(hipEventRecord(ev[4], s));
+        HIP_TRY(hipEventSynchronize(ev[4]));
+        for (int k = 0; k < 4; ++k) {
+            float t;
+            HIP_TRY(hipEventElapsedTime(&t, ev[k], ev[k + 1]));
+            ms[k] = t / (float)iters;
+        }
+        for (auto &e : ev) HIP_TRY(hipEventDestroy(e));
+        return SMOL_OK;
+    }
+};
+}  // namespace
+
+// Times the kernels the integrator runs: vectors in the transposed layout.
+extern "C" int smol_profile_rhs(int64_t M, int32_t R, const double *U, const double *V,
+                                double lambda, const double *n, double *dndt, int32_t iters,
+                                float *ms_out, void *stream)
+{
+    int rc = check_common(M, R, U, V, lambda);
+    if (rc) return rc;
+    if (!n || !dndt || n == dndt || iters < 1 || !ms_out) return SMOL_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Plan *p;
+    DevRoots *r;
+    if ((rc = get_plan(M, R, SMOL_FP64, &p))) return rc;
+    if ((rc = get_roots(p->dev, &r))) return rc;
+    if ((rc = alloc_integ(p))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const IntegDev I = integ_dev(p, r);
+    hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, U, I.Ut, M, R, M, I.Mt, p->logL);
+    hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, V, I.Vt, M, R, M, I.Mt, p->logL);
+    hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, n, I.nb[0], M, 1, M, I.Mt, p->logL);
+    RhsPlanDev P = dev_plan(p, r, I.Ut, I.Vt, lambda);
+    P.tr = 1;
+    P.ustride = I.Mt;
+    Pro in{A_COMBINE, I.nb[0], nullptr, 0.0, nullptr};
+    Epi ep{};
+    ep.mode = C_RHS;
+    ep.y = I.nb[0];
+    ep.out = I.kslot[0];
+    rc = with_shape<ProfileRhs>(p->logL, P, in, ep, iters, ms_out, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_from_tr, dim3(256), dim3(256), 0, s, I.kslot[0], dndt, M, p->logL);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    return SMOL_OK;
+}
+
+// ---- entry points not built yet ------------------------------------------
+extern "C" int smol_integrate_batch(int32_t, const smol_instance *, int32_t, int32_t,
+                                    const smol_options *, smol_stats *, void *)
+{
+    return SMOL_EUNSUPPORTED;
+}
+extern "C" int smol_proposer_set(const float *, int32_t, void *) { return SMOL_EUNSUPPORTED; }
+extern "C" int smol_proposer_train(const float *, const float *, int64_t, float *, int32_t,
+                                   int32_t, float, float, uint64_t, float *, void *)
+{
+    return SMOL_EUNSUPPORTED;
+}

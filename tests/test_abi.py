@@ -1,0 +1,60 @@
+"""The C-ABI library loads and exports every entry point its header declares
+(no GPU needed: only calls that fail validation before touching the device)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "smol.h")).read()
+    return sorted(set(re.findall(r"\b(smol_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2407_16559_amd as smol
+    if not os.path.exists(smol.LIB_PATH):
+        pytest.skip("libsmol.so not built")
+    return smol.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert "smol_rhs" in names and "smol_integrate" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_strerror_and_version(lib):
+    import paper_2407_16559_amd as smol
+    assert smol.version()
+    for code in range(0, -8, -1):
+        assert smol.strerror(code) != "unknown status code"
+    assert smol.strerror(-99) == "unknown status code"
+
+
+def test_validation_before_device(lib):
+    """Bad sizes, ranks, lambdas and null pointers are rejected up front."""
+    p = ctypes.c_void_p(16)
+    assert lib.smol_rhs(0, 3, p, p, 0.0, p, ctypes.c_void_p(32), 0, None) == -1
+    assert lib.smol_rhs(10, 0, p, p, 0.0, p, ctypes.c_void_p(32), 0, None) == -1
+    assert lib.smol_rhs(10, 17, p, p, 0.0, p, ctypes.c_void_p(32), 0, None) == -1
+    assert lib.smol_rhs(10, 3, p, p, -1.0, p, ctypes.c_void_p(32), 0, None) == -1
+    assert lib.smol_rhs(10, 3, p, p, float("nan"), p, ctypes.c_void_p(32), 0, None) == -1
+    assert lib.smol_rhs(10, 3, None, p, 0.0, p, ctypes.c_void_p(32), 0, None) == -1
+    assert lib.smol_rhs(10, 3, p, p, 0.0, p, p, 0, None) == -1          # dndt aliases n
+    assert lib.smol_rhs(10, 3, p, p, 0.0, p, ctypes.c_void_p(32), 7, None) == -1
+    assert lib.smol_rhs(1 << 21, 3, p, p, 0.0, p, ctypes.c_void_p(32), 0, None) == -7
+
+
+def test_no_fallback_without_library(monkeypatch, tmp_path):
+    """The binding never computes on its own: a missing library raises."""
+    import paper_2407_16559_amd as smol
+    monkeypatch.setattr(smol, "_lib", None)
+    monkeypatch.setattr(smol, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError):
+        smol.lib()
