@@ -134,35 +134,31 @@ __device__ inline Epi stage_epi(const IntegDev &I, const IntegCtl &c, const Tabl
         ep.mode = C_INIT1;
         ep.y = I.ybuf;
         ep.ks[0] = kvec(I, c, S, 1);
+        ep.coef[0] = 1.0;  // marks the slot as used: f0
         ep.nks = 1;
     } else if (stage < S) {
+        // fixed slots j-1 for k_j (zero coefficients are skipped at use)
         ep.mode = C_STAGE;
         ep.y = I.ybuf;
         ep.out = kvec(I, c, S, stage);
         ep.ynext = (stage + 1 == S) ? I.nb[c.cur ^ 1] : I.ybuf;
-        int m = 0;
-        for (int j = 1; j < stage; ++j) {
-            const double a = T.a[stage][j - 1];
-            if (a != 0.0) {
-                ep.ks[m] = kvec(I, c, S, j);
-                ep.coef[m++] = a;
-            }
+#pragma unroll
+        for (int j = 1; j < SMOL_MAX_STAGE; ++j) {
+            ep.ks[j - 1] = kvec(I, c, S, j < S ? j : 1);
+            ep.coef[j - 1] = j < stage ? T.a[stage][j - 1] : 0.0;
         }
-        ep.nks = m;
+        ep.nks = stage - 1;
         ep.cS = T.a[stage][stage - 1];
     } else {
         ep.mode = C_LAST;
         ep.y = I.nb[c.cur ^ 1];
         ep.out = kvec(I, c, S, S);
-        int m = 0;
-        for (int j = 1; j < S; ++j) {
-            const double dj = T.d[j - 1];
-            if (dj != 0.0) {
-                ep.ks[m] = kvec(I, c, S, j);
-                ep.coef[m++] = dj;
-            }
+#pragma unroll
+        for (int j = 1; j < SMOL_MAX_STAGE; ++j) {
+            ep.ks[j - 1] = kvec(I, c, S, j < S ? j : 1);
+            ep.coef[j - 1] = j < S ? T.d[j - 1] : 0.0;
         }
-        ep.nks = m;
+        ep.nks = S - 1;
         ep.cS = T.d[S - 1];
     }
     return ep;

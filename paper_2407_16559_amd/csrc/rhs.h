@@ -342,13 +342,53 @@ struct PhaseC {
     static __host__ __device__ int units() { return HALF / COLS; }
     static __host__ __device__ int jobs() { return units(); }
 
+    static constexpr int KMAX = 6;  // stage vectors an epilogue combines
+    static constexpr int RPRE = 4;  // ranks whose U, V are prefetched
+
     __device__ static void run(const RhsPlanDev &P, const Epi &ep, int unit, cd *lds)
     {
-        __shared__ double sh[SMOL_WAVES * SMOL_EPART];
+        __shared__ double sh[SMOL_WAVES * 16];
         const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
         const int64_t M = P.M;
         const int R = P.R;
         const double lam = P.lam;
+        const int mode = ep.mode;
+        const bool need_n = mode != C_RHS;
+        const bool need_v = mode == C_STAGE;
+        const int nk = (mode == C_STAGE || mode == C_LAST || mode == C_INIT1) ? ep.nks : 0;
+        const int rp = R < RPRE ? R : RPRE;
+        // ---- prefetch every per-size input of this thread's outputs
+        int64_t qv[PP], sz[PP];
+        double yv[PP], nv[PP], kv[PP][KMAX], Uv[PP][RPRE], Vv[PP][RPRE];
+#pragma unroll
+        for (int j = 0; j < PP; ++j) {
+            const int e = tid + j * SMOL_WG;
+            qv[j] = -1;
+            sz[j] = 0;
+            yv[j] = nv[j] = 0.0;
+            if (e < NPOS) {
+                const int b = e % (N1 / 2), hh = (e / (N1 / 2)) & 1, f = e / N1;
+                const int64_t m = unit * COLS + f + hh * HALF + (int64_t)N2 * b;
+                if (m <= M - 2) {
+                    const int64_t q = pos_of(P, m + 1);
+                    qv[j] = q;
+                    sz[j] = m + 2;
+                    yv[j] = ep.y[q];
+                    if (need_n) nv[j] = ep.n[q];
+#pragma unroll
+                    for (int k = 0; k < KMAX; ++k)
+                        kv[j][k] = (k < nk && ep.coef[k] != 0.0) ? ep.ks[k][q] : 0.0;
+#pragma unroll
+                    for (int a = 0; a < RPRE; ++a) {
+                        if (a < rp) {
+                            Uv[j][a] = P.U[(int64_t)a * P.ustride + q];
+                            if (need_v) Vv[j][a] = P.V[(int64_t)a * P.ustride + q];
+                        }
+                    }
+                }
+            }
+        }
+        // ---- inverse DFT over k1 of this unit's packed columns (wave 0)
         if (w == 0) {
             const int f = lane / F::G, g = lane % F::G;
             const int ac = unit * COLS + f;
@@ -366,38 +406,34 @@ struct PhaseC {
             }
         }
         __syncthreads();
+        // ---- finish: S, then the fused epilogue
         const double invL = 1.0 / (double)(1LL << P.logL);
         double acc[SMOL_EPART];
 #pragma unroll
         for (int q = 0; q < SMOL_EPART; ++q) acc[q] = 0.0;
-        int64_t posv[PP + 1], sizev[PP + 1];
-        int np = 0;
+        double yn[PP];
 #pragma unroll
         for (int j = 0; j < PP; ++j) {
-            const int e = tid + j * SMOL_WG;
-            posv[j] = -1;
-            if (e < NPOS) {
+            yn[j] = 0.0;
+            if (qv[j] >= 0) {
+                const int e = tid + j * SMOL_WG;
                 const int b = e % (N1 / 2), hh = (e / (N1 / 2)) & 1, f = e / N1;
-                const int64_t m = unit * COLS + f + hh * HALF + (int64_t)N2 * b;
-                if (m <= M - 2) {
-                    const cd val = lds[f * (N1 / 2) + b];
-                    const double c = (hh ? val.y : val.x) * invL;
-                    const int64_t idx = m + 1;
-                    const int64_t q = pos_of(P, idx);
-                    double dsum = 0.0;
-                    for (int al = 0; al < R; ++al)
-                        dsum = fma(P.U[(int64_t)al * P.ustride + q], P.red[4 * al], dsum);
-                    const double S = fma(-(1.0 + lam) * ep.y[q], dsum, 0.5 * c);
-                    epilogue(ep, q, (double)(idx + 1), S, acc);
-                    posv[j] = q;
-                    sizev[j] = idx + 1;
-                    ++np;
-                }
+                const cd val = lds[f * (N1 / 2) + b];
+                const double c = (hh ? val.y : val.x) * invL;
+                double dsum = 0.0;
+#pragma unroll
+                for (int a = 0; a < RPRE; ++a)
+                    if (a < rp) dsum = fma(Uv[j][a], P.red[4 * a], dsum);
+                for (int a = RPRE; a < R; ++a)
+                    dsum = fma(P.U[(int64_t)a * P.ustride + qv[j]], P.red[4 * a], dsum);
+                const double S = fma(-(1.0 + lam) * yv[j], dsum, 0.5 * c);
+                yn[j] = finish(ep, qv[j], (double)sz[j], S, yv[j], nv[j], kv[j], nk, acc);
             }
         }
-        // size 1 (index 0): monomer balance with the shattering gains
-        posv[PP] = -1;
-        if (unit == 0 && tid == 0) {
+        // ---- size 1 (index 0): monomer balance with the shattering gains
+        const bool mono = unit == 0 && tid == 0;
+        double yn1 = 0.0;
+        if (mono) {
             const double y1 = ep.y[0];
             double d1 = 0.0, g1 = 0.0, pairs = 0.0;
             for (int al = 0; al < R; ++al) {
@@ -410,41 +446,57 @@ struct PhaseC {
                 pairs = fma(pp, q, fma(r, t, pairs));
             }
             const double S1 = -y1 * d1 + 0.5 * lam * pairs + lam * y1 * g1;
-            epilogue(ep, 0, 1.0, S1, acc);
-            posv[PP] = 0;
-            sizev[PP] = 1;
-        }
-        (void)np;
-        if (ep.mode == C_STAGE) {
-            // reductions of the next stage state, rank by rank
-            for (int al = 0; al < R; ++al) {
-                double s4[4] = {0.0, 0.0, 0.0, 0.0};
-                const double *Ua = P.U + (int64_t)al * P.ustride, *Va = P.V + (int64_t)al * P.ustride;
+            double k1v[KMAX];
 #pragma unroll
-                for (int j = 0; j <= PP; ++j) {
-                    const int64_t q = posv[j];
-                    if (q >= 0) {
-                        const double yn = ep.ynext[q];
-                        const double x = Va[q] * yn;
-                        s4[0] += x;
-                        if (sizev[j] >= 2) {
-                            const double sz = (double)sizev[j], u = Ua[q] * yn;
-                            s4[1] = fma(sz, x, s4[1]);
-                            s4[2] += u;
-                            s4[3] = fma(sz, u, s4[3]);
+            for (int k = 0; k < KMAX; ++k) k1v[k] = (k < nk && ep.coef[k] != 0.0) ? ep.ks[k][0] : 0.0;
+            yn1 = finish(ep, 0, 1.0, S1, y1, need_n ? ep.n[0] : 0.0, k1v, nk, acc);
+        }
+        if (mode == C_STAGE) {
+            // reductions of the next stage state, four ranks per pass
+            for (int a0 = 0; a0 < R; a0 += 4) {
+                double s4[16];
+#pragma unroll
+                for (int k = 0; k < 16; ++k) s4[k] = 0.0;
+#pragma unroll
+                for (int j = 0; j < PP; ++j) {
+                    if (qv[j] >= 0) {
+                        const double szd = (double)sz[j];
+#pragma unroll
+                        for (int a = 0; a < 4; ++a) {
+                            if (a0 + a < R) {
+                                double u, x;
+                                if (a0 == 0) {
+                                    u = Uv[j][a];
+                                    x = Vv[j][a];
+                                } else {
+                                    u = P.U[(int64_t)(a0 + a) * P.ustride + qv[j]];
+                                    x = P.V[(int64_t)(a0 + a) * P.ustride + qv[j]];
+                                }
+                                x *= yn[j];
+                                u *= yn[j];
+                                s4[4 * a] += x;
+                                s4[4 * a + 1] = fma(szd, x, s4[4 * a + 1]);
+                                s4[4 * a + 2] += u;
+                                s4[4 * a + 3] = fma(szd, u, s4[4 * a + 3]);
+                            }
                         }
                     }
                 }
+                if (mono)
+                    for (int a = 0; a < 4 && a0 + a < R; ++a)
+                        s4[4 * a] += P.V[(int64_t)(a0 + a) * P.ustride] * yn1;
+                const int na = (R - a0) < 4 ? (R - a0) : 4;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) s4[k] = wave_sum(s4[k]);
+                for (int k = 0; k < 16; ++k)
+                    if (k < 4 * na) s4[k] = wave_sum(s4[k]);
                 if (lane == 0)
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) sh[w * 4 + k] = s4[k];
+                    for (int k = 0; k < 4 * na; ++k) sh[w * 16 + k] = s4[k];
                 __syncthreads();
-                if (tid < 4) P.red_part[((int64_t)unit * R + al) * 4 + tid] = sum_waves(sh, 4, tid);
+                if (tid < 4 * na)
+                    P.red_part[((int64_t)unit * R + a0) * 4 + tid] = sum_waves(sh, 16, tid);
                 __syncthreads();
             }
-        } else if (ep.mode != C_RHS) {
+        } else if (mode != C_RHS) {
 #pragma unroll
             for (int q = 0; q < SMOL_EPART; ++q) acc[q] = wave_sum(acc[q]);
             if (lane == 0)
@@ -456,52 +508,56 @@ struct PhaseC {
         }
     }
 
-    // per-element epilogue at position q (size s); accumulates partials
-    __device__ static void epilogue(const Epi &ep, int64_t q, double s, double S, double *acc)
+    // Store S and the mode's result at position q (size s); returns the next
+    // stage state (C_STAGE) and accumulates partial sums.
+    __device__ static double finish(const Epi &ep, int64_t q, double s, double S, double y,
+                                    double n, const double (&k)[KMAX], int nk, double *acc)
     {
         switch (ep.mode) {
         case C_RHS:
             ep.out[q] = S;
-            break;
+            return 0.0;
         case C_STAGE: {
             ep.out[q] = S;
             double a = ep.cS * S;
-            for (int j = 0; j < ep.nks; ++j) a = fma(ep.coef[j], ep.ks[j][q], a);
-            ep.ynext[q] = fma(ep.h, a, ep.n[q]);
-            break;
+#pragma unroll
+            for (int j = 0; j < KMAX; ++j)
+                if (j < nk) a = fma(ep.coef[j], k[j], a);  // zero coefficients: k[j] = 0
+            const double yn = fma(ep.h, a, n);
+            ep.ynext[q] = yn;
+            return yn;
         }
         case C_LAST: {
             ep.out[q] = S;
             double e = ep.cS * S;
-            for (int j = 0; j < ep.nks; ++j) e = fma(ep.coef[j], ep.ks[j][q], e);
+#pragma unroll
+            for (int j = 0; j < KMAX; ++j)
+                if (j < nk) e = fma(ep.coef[j], k[j], e);
             e *= ep.h;
-            const double yn = ep.y[q], y0 = ep.n[q];
-            const double sc = fma(ep.rtol, fmax(fabs(y0), fabs(yn)), ep.atol);
+            const double sc = fma(ep.rtol, fmax(fabs(n), fabs(y)), ep.atol);
             const double r = e / sc;
             acc[0] = fma(r, r, acc[0]);
-            acc[1] += yn;
-            acc[2] = fma(s, yn, acc[2]);
-            acc[3] = fma(s * s, yn, acc[3]);
-            acc[4] = fma(s * s * s, yn, acc[4]);
-            if (!isfinite(yn)) acc[5] += 1.0;
-            break;
+            acc[1] += y;
+            acc[2] = fma(s, y, acc[2]);
+            acc[3] = fma(s * s, y, acc[3]);
+            acc[4] = fma(s * s * s, y, acc[4]);
+            if (!isfinite(y)) acc[5] += 1.0;
+            return 0.0;
         }
         case C_INIT0: {
             ep.out[q] = S;
-            const double y0 = ep.n[q];
-            const double sc = fma(ep.rtol, fabs(y0), ep.atol);
-            const double a = y0 / sc, b = S / sc;
+            const double sc = fma(ep.rtol, fabs(y), ep.atol);
+            const double a = y / sc, b = S / sc;
             acc[0] = fma(a, a, acc[0]);
             acc[1] = fma(b, b, acc[1]);
-            if (!isfinite(y0)) acc[5] += 1.0;
-            break;
+            if (!isfinite(y)) acc[5] += 1.0;
+            return 0.0;
         }
-        default: {  // C_INIT1
-            const double y0 = ep.n[q];
-            const double sc = fma(ep.rtol, fabs(y0), ep.atol);
-            const double d = (S - ep.ks[0][q]) / sc;
+        default: {  // C_INIT1: y = n0 + h0 f0, n = n0, k[0] = f0
+            const double sc = fma(ep.rtol, fabs(n), ep.atol);
+            const double d = (S - k[0]) / sc;
             acc[0] = fma(d, d, acc[0]);
-            break;
+            return 0.0;
         }
         }
     }

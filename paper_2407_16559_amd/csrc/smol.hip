@@ -13,6 +13,7 @@
 #include "integrate.h"
 
 #define SMOL_VERSION "0.1.0"
+#define SMOL_GRAPH_ATTEMPTS 4
 
 // --------------------------------------------------------------------------
 // Kernels (multi-launch form of the three phases)
@@ -548,7 +549,8 @@ IntegDev integ_dev(const Plan *p, const DevRoots *r)
     return I;
 }
 
-// Capture one step attempt (stages 2..S, controller) as a graph.
+// Capture SMOL_GRAPH_ATTEMPTS step attempts (stages 2..S, controller) as
+// one graph.
 int get_step_graph(Plan *p, const IntegDev &I, int method, hipGraphExec_t *out)
 {
     if (p->graph[method]) {
@@ -556,12 +558,15 @@ int get_step_graph(Plan *p, const IntegDev &I, int method, hipGraphExec_t *out)
         return SMOL_OK;
     }
     const int S = method == SMOL_DP54 ? 7 : 4;
-    const int nC = with_shape<PhaseCJobs>(p->logL);
     hipGraph_t g;
     HIP_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
     int rc = SMOL_OK;
-    for (int st = 2; st <= S && rc == SMOL_OK; ++st) rc = with_shape<LaunchStage>(p->logL, I, st, p->cap);
-    hipLaunchKernelGGL(k_ctrl, dim3(1), dim3(SMOL_WG), 0, p->cap, I, nC);
+    const int nC = with_shape<PhaseCJobs>(p->logL);
+    for (int a = 0; a < SMOL_GRAPH_ATTEMPTS; ++a) {
+        for (int st = 2; st <= S && rc == SMOL_OK; ++st)
+            rc = with_shape<LaunchStage>(p->logL, I, st, p->cap);
+        hipLaunchKernelGGL(k_ctrl, dim3(1), dim3(SMOL_WG), 0, p->cap, I, nC);
+    }
     hipError_t e = hipStreamEndCapture(p->cap, &g);
     if (rc) return rc;
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
@@ -733,7 +738,7 @@ extern "C" int smol_integrate_ex(int64_t M, int32_t R, const double *U, const do
     hipGraphExec_t ge;
     if ((rc = get_step_graph(p, I, method, &ge))) return rc;
     // replay step attempts; poll the control block between chunks
-    int64_t chunk = 4;
+    int64_t chunk = 1;
     for (;;) {
         for (int64_t i = 0; i < chunk; ++i) HIP_TRY(hipGraphLaunch(ge, s));
         HIP_TRY(hipMemcpyAsync(p->host, p->ctl, sizeof(IntegCtl), hipMemcpyDeviceToHost, s));
@@ -741,8 +746,8 @@ extern "C" int smol_integrate_ex(int64_t M, int32_t R, const double *U, const do
         if (c.done) break;
         double est = (c.h > 0) ? (c.t_end - c.t) / c.h : 1e9;
         if (!(est < 1e9)) est = 1e9;
-        chunk = (int64_t)(0.8 * est) + 1;
-        if (chunk > 256) chunk = 256;
+        chunk = (int64_t)(0.8 * est / SMOL_GRAPH_ATTEMPTS) + 1;
+        if (chunk > 64) chunk = 64;
         if (chunk < 1) chunk = 1;
     }
     hipLaunchKernelGGL(k_from_tr, dim3(256), dim3(256), 0, s, I.nb[c.cur], n_out, M, p->logL);
