@@ -1,8 +1,9 @@
 // Wavefront-level Stockham FFT for lengths N = 2^3 .. 2^10.
 //
 // One transform of length N is owned by G = N/E lanes of a single wave64,
-// each lane holding E complex doubles in registers (E = 8, or 16 for
-// N = 1024); a wave runs B = 64/G transforms side by side.  Radix-E
+// each lane holding E complex values in registers (E = 8, or 16 for
+// N = 1024); a wave runs B = 64/G transforms side by side.  The complex type
+// C is cd (FP64) or cff (float-float); the code is the same for both.  Radix-E
 // butterflies run in registers; the exchanges between stages go through a
 // per-transform LDS region of N entries, ordered by wave_sync() only (no
 // workgroup barrier).  Stockham's self-sorting form keeps both the input and
@@ -12,6 +13,32 @@
 // the last stage leaves the spectrum in registers for a direct store.
 #pragma once
 #include "common.h"
+#include "ff.h"
+
+// conversions from FP64 complex values (unit roots, inputs)
+template <class C>
+__device__ __forceinline__ C from_cd(cd v);
+template <>
+__device__ __forceinline__ cd from_cd<cd>(cd v)
+{
+    return v;
+}
+template <>
+__device__ __forceinline__ cff from_cd<cff>(cd v)
+{
+    return cff{ff_from(v.x), ff_from(v.y)};
+}
+template <class C>
+__device__ __forceinline__ C czero()
+{
+    return from_cd<C>(cd{0.0, 0.0});
+}
+__device__ __forceinline__ double re_d(cd v) { return v.x; }
+__device__ __forceinline__ double im_d(cd v) { return v.y; }
+__device__ __forceinline__ double re_d(cff v) { return ff_to(v.x); }
+__device__ __forceinline__ double im_d(cff v) { return ff_to(v.y); }
+
+constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
 
 template <int N>
 struct FftShape {
@@ -52,62 +79,64 @@ __device__ __forceinline__ double c16(int m)
 __device__ __forceinline__ double s16(int m) { return c16(m <= 4 ? 4 - m : m - 4); }
 
 // multiply by W_R^k (forward: exp(-2 pi i k / R)), k < R/2, R | 16
-template <int R, bool INV>
-__device__ __forceinline__ cd twiddle_const(cd a, int k)
+template <int R, bool INV, class C>
+__device__ __forceinline__ C twiddle_const(C a, int k)
 {
     const int m = k * (16 / R);  // angle 2 pi m / 16, 0 <= m < 8
     if (m == 0) return a;
     if (m == 4) return crot<INV>(a);
     const double c = c16(m);
     const double s = INV ? s16(m) : -s16(m);  // forward uses exp(-i theta)
-    return cd{fma(a.x, c, -a.y * s), fma(a.x, s, a.y * c)};
+    if constexpr (__is_same(C, cd)) {
+        return cd{fma(a.x, c, -a.y * s), fma(a.x, s, a.y * c)};
+    } else {
+        return cmul(a, from_cd<C>(cd{c, s}));
+    }
 }
 
-template <int R, bool INV>
+template <int R, bool INV, class C>
 struct Dft {
-    __device__ __forceinline__ static void run(cd (&v)[R])
+    __device__ __forceinline__ static void run(C (&v)[R])
     {
-        cd e[R / 2], o[R / 2];
+        C e[R / 2], o[R / 2];
 #pragma unroll
         for (int i = 0; i < R / 2; ++i) {
             e[i] = v[2 * i];
             o[i] = v[2 * i + 1];
         }
-        Dft<R / 2, INV>::run(e);
-        Dft<R / 2, INV>::run(o);
+        Dft<R / 2, INV, C>::run(e);
+        Dft<R / 2, INV, C>::run(o);
 #pragma unroll
         for (int k = 0; k < R / 2; ++k) {
-            cd t = twiddle_const<R, INV>(o[k], k);
+            C t = twiddle_const<R, INV>(o[k], k);
             v[k] = cadd(e[k], t);
             v[k + R / 2] = csub(e[k], t);
         }
     }
 };
-template <bool INV>
-struct Dft<2, INV> {
-    __device__ __forceinline__ static void run(cd (&v)[2])
+template <bool INV, class C>
+struct Dft<2, INV, C> {
+    __device__ __forceinline__ static void run(C (&v)[2])
     {
-        cd a = v[0], b = v[1];
+        C a = v[0], b = v[1];
         v[0] = cadd(a, b);
         v[1] = csub(a, b);
     }
 };
-template <bool INV>
-struct Dft<1, INV> {
-    __device__ __forceinline__ static void run(cd (&)[1]) {}
+template <bool INV, class C>
+struct Dft<1, INV, C> {
+    __device__ __forceinline__ static void run(C (&)[1]) {}
 };
 
 // ---------------------------------------------------------------------
 // Stockham stages.
 // ---------------------------------------------------------------------
 
-constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
-
 // w^q for q = 0..R-1 by a multiplication tree of depth <= 4 (a few ulps).
-template <int R>
-__device__ __forceinline__ void pow_tree(cd w, cd (&o)[R])
+template <int R, class C>
+__device__ __forceinline__ void pow_tree(C w, C (&o)[R])
 {
-    o[0] = cmk(1.0, 0.0);
+    o[0] = from_cd<C>(cd{1.0, 0.0});
     if constexpr (R > 1) o[1] = w;
     if constexpr (R > 2) o[2] = cmul(w, w);
     if constexpr (R > 3) o[3] = cmul(o[2], w);
@@ -125,17 +154,15 @@ __device__ __forceinline__ void pow_tree(cd w, cd (&o)[R])
 }
 
 // Per-lane base twiddles of every stage after the first, W_{Ns r}^k with
-// k = j mod Ns, loaded once before the data arrives.
-template <int N, bool INV>
+// k = j mod Ns, loaded once before the data arrives (split into float-float
+// from the FP64 table when C = cff).
+template <int N, bool INV, class C>
 struct FftTw {
     using S = FftShape<N>;
     static constexpr int PMAX = (S::E / 2 > 0) ? S::E / 2 : 1;
-    cd w[S::NST > 1 ? S::NST - 1 : 1][PMAX];
+    C w[S::NST > 1 ? S::NST - 1 : 1][PMAX];
 
-    __device__ __forceinline__ void load(int g, const Roots &rt)
-    {
-        load_st<1>(g, rt);
-    }
+    __device__ __forceinline__ void load(int g, const Roots &rt) { load_st<1>(g, rt); }
     template <int ST>
     __device__ __forceinline__ void load_st(int g, const Roots &rt)
     {
@@ -147,17 +174,17 @@ struct FftTw {
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const int k = (g + p * S::G) & ((1 << LNS) - 1);
-                w[ST - 1][p] = root_small<INV>(rt, LNS + LR, k);
+                w[ST - 1][p] = from_cd<C>(root_small<INV>(rt, LNS + LR, k));
             }
             load_st<ST + 1>(g, rt);
         }
     }
 };
 
-template <int N, bool INV, int ST>
+template <int N, bool INV, int ST, class C>
 struct FftStage {
     using S = FftShape<N>;
-    __device__ __forceinline__ static void run(cd (&v)[S::E], cd *buf, int g, const FftTw<N, INV> &tw)
+    __device__ __forceinline__ static void run(C (&v)[S::E], C *buf, int g, const FftTw<N, INV, C> &tw)
     {
         constexpr int r = S::radix(ST);
         constexpr int LR = ilog2c(r);
@@ -174,16 +201,16 @@ struct FftStage {
         }
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            cd t[r];
+            C t[r];
 #pragma unroll
             for (int q = 0; q < r; ++q) t[q] = v[p + q * P];
             if constexpr (Ns > 1) {
-                cd wq[r];
+                C wq[r];
                 pow_tree<r>(tw.w[ST - 1][p], wq);
 #pragma unroll
                 for (int q = 1; q < r; ++q) t[q] = cmul(t[q], wq[q]);
             }
-            Dft<r, INV>::run(t);
+            Dft<r, INV, C>::run(t);
 #pragma unroll
             for (int q = 0; q < r; ++q) v[p + q * P] = t[q];
         }
@@ -197,28 +224,28 @@ struct FftStage {
 #pragma unroll
                 for (int q = 0; q < r; ++q) buf[base + q * Ns] = v[p + q * P];
             }
-            FftStage<N, INV, ST + 1>::run(v, buf, g, tw);
+            FftStage<N, INV, ST + 1, C>::run(v, buf, g, tw);
         }
     }
 };
 
 // Transform the N values held by lanes g = 0..G-1 (layout above) in place.
 // buf: this transform's LDS region (N entries); tw: loaded base twiddles.
-template <int N, bool INV>
-__device__ __forceinline__ void wave_fft(cd (&v)[FftShape<N>::E], cd *buf, int g,
-                                         const FftTw<N, INV> &tw)
+template <int N, bool INV, class C>
+__device__ __forceinline__ void wave_fft(C (&v)[FftShape<N>::E], C *buf, int g,
+                                         const FftTw<N, INV, C> &tw)
 {
-    FftStage<N, INV, 0>::run(v, buf, g, tw);
+    FftStage<N, INV, 0, C>::run(v, buf, g, tw);
 }
 
 // Lane's four-step twiddles W_L^{e (g + i G)}, i = 0..E-1, from two table
 // lookups (base W_L^{e g} and step W_L^{e G}) and a power tree.
-template <int E, bool INV>
+template <int E, bool INV, class C>
 __device__ __forceinline__ void step_twiddles(const Roots &rt, int logL, uint32_t e, int g, int G,
-                                              cd (&o)[E])
+                                              C (&o)[E])
 {
-    const cd base = root_big<INV>(rt, logL, e * (uint32_t)g);
-    const cd step = root_big<INV>(rt, logL, e * (uint32_t)G);
+    const C base = from_cd<C>(root_big<INV>(rt, logL, e * (uint32_t)g));
+    const C step = from_cd<C>(root_big<INV>(rt, logL, e * (uint32_t)G));
     pow_tree<E>(step, o);
 #pragma unroll
     for (int i = 0; i < E; ++i) o[i] = cmul(base, o[i]);

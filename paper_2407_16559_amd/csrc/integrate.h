@@ -70,7 +70,7 @@ struct IntegDev {
     double *nb[2];
     double *kslot[8];
     double *ybuf;
-    cd *Z, *Qp;
+    void *Z, *Qp;
     double *red_part, *red, *epart;
     Roots rt;
     const float *mlp;  // proposer weights (may be null)

@@ -53,8 +53,8 @@ struct RhsPlanDev {
     int64_t ustride;      // distance between the rank rows of U and V
     double lam;
     const double *U, *V;  // alpha-major, rows of ustride
-    cd *Z;                // R * L
-    cd *Qp;               // L / 2
+    void *Z;              // R * L complex (cd or cff)
+    void *Qp;             // L / 2 complex
     double *red_part;     // [jobs][R][4]
     double *red;          // [R][4]: w, t, r, p
     Roots rt;
@@ -109,11 +109,27 @@ __device__ __forceinline__ double sum_waves(const double *sh, int nq, int q)
     return a;
 }
 
+// acc + a^2 - conj(b)^2 (one rank's term of the spectral product, times 4i)
+__device__ __forceinline__ cd spec_term(cd acc, cd a, cd b)
+{
+    const double re = (a.x * a.x - a.y * a.y) - (b.x * b.x - b.y * b.y);
+    const double im = 2.0 * (a.x * a.y + b.x * b.y);
+    return cd{acc.x + re, acc.y + im};
+}
+__device__ __forceinline__ cff spec_term(cff acc, cff a, cff b)
+{
+    const cff bc = cconj(b);
+    return cadd(acc, csub(cmul(a, a), cmul(bc, bc)));
+}
+// x / (4i) = (x.y, -x.x) / 4 (exact)
+__device__ __forceinline__ cd div4i(cd x) { return cd{0.25 * x.y, -0.25 * x.x}; }
+__device__ __forceinline__ cff div4i(cff x) { return cff{ff_scale2(x.y, 0.25f), ff_scale2(ff_neg(x.x), 0.25f)}; }
+
 // --------------------------------------------------------------------------
 // Phase A
 // --------------------------------------------------------------------------
 
-template <int N1, int N2>
+template <int N1, int N2, class C>
 struct PhaseA {
     using F = FftShape<N1>;
     static constexpr int COLS = (F::B < N2) ? F::B : N2;             // per wave
@@ -125,7 +141,7 @@ struct PhaseA {
     static __host__ __device__ int red_jobs() { return NG; }
 
     // one unit = (rank al, group of GA columns); whole workgroup
-    __device__ static void run(const RhsPlanDev &P, const Pro &in, int unit, cd *lds)
+    __device__ static void run(const RhsPlanDev &P, const Pro &in, int unit, C *lds)
     {
         __shared__ double sh[SMOL_WAVES * 4];
         const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
@@ -135,18 +151,18 @@ struct PhaseA {
         const bool active = (w < WUSED) && (f < COLS);
         const int64_t M = P.M;
         const double *Ua = P.U + (int64_t)al * P.ustride, *Va = P.V + (int64_t)al * P.ustride;
-        FftTw<N1, false> tw;
-        cd t4[F::E];
+        FftTw<N1, false, C> tw;
+        C t4[F::E];
         if (active) {
             tw.load(g, P.rt);
             step_twiddles<F::E, false>(P.rt, P.logL, (uint32_t)n2, g, F::G, t4);
         }
-        cd v[F::E];
+        C v[F::E];
         double sw = 0, st = 0, sr = 0, sp = 0;
         const bool comb = in.mode == A_COMBINE;
 #pragma unroll
         for (int i = 0; i < F::E; ++i) {
-            v[i] = cmk(0.0, 0.0);
+            v[i] = czero<C>();
             if (i < F::E / 2 && active) {
                 const int64_t idx = (int64_t)(g + i * F::G) * N2 + n2;
                 if (idx < M) {
@@ -157,7 +173,7 @@ struct PhaseA {
                         if (in.ywrite && al == 0) in.ywrite[q] = yv;
                     }
                     const double u = Ua[q] * yv, x = Va[q] * yv;
-                    if (idx < M - 1) v[i] = cmk(u, x);
+                    if (idx < M - 1) v[i] = from_cd<C>(cd{u, x});
                     if (comb) {
                         const double s = (double)(idx + 1);
                         sw += x;
@@ -185,7 +201,7 @@ struct PhaseA {
             sr += u;
             sp = fma(s, u, sp);
         }
-        cd *wl = lds + w * 64 * F::E;
+        C *wl = lds + w * 64 * F::E;
         if (active) {
             wave_fft<N1, false>(v, wl + f * N1, g, tw);
             wave_sync();
@@ -194,7 +210,7 @@ struct PhaseA {
         }
         __syncthreads();
         // store rows of GA consecutive columns
-        cd *Za = P.Z + ((int64_t)al << P.logL) + grp * GA;
+        C *Za = (C *)P.Z + ((int64_t)al << P.logL) + grp * GA;
         for (int e = tid; e < GA * N1; e += SMOL_WG) {
             const int c = e % GA, k1 = e / GA;
             Za[(int64_t)k1 * N2 + c] = lds[(c / COLS) * 64 * F::E + (c % COLS) * N1 + k1];
@@ -220,7 +236,7 @@ struct PhaseA {
 // Phase B
 // --------------------------------------------------------------------------
 
-template <int N1, int N2>
+template <int N1, int N2, class C>
 struct PhaseB {
     using F = FftShape<N2>;
     static constexpr int SLOTS = SMOL_WAVES * F::B;  // row transforms per round
@@ -230,18 +246,18 @@ struct PhaseB {
     static constexpr int LDS = SLOTS * N2 + 2 * N2;
 
     // unit k1 in [0, N1/2]; whole workgroup
-    __device__ static void run(const RhsPlanDev &P, int k1, cd *lds)
+    __device__ static void run(const RhsPlanDev &P, int k1, C *lds)
     {
         const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
         const int f = lane / F::G, g = lane % F::G;
         const int slot = wave * F::B + f;
         const int k1p = (N1 - k1) & (N1 - 1);
         const bool single = (k1 == k1p);  // k1 = 0 or N1/2
-        cd *rows = lds;
-        cd *P1 = lds + SLOTS * N2, *P2 = P1 + N2;
-        FftTw<N2, false> twf;
+        C *rows = lds;
+        C *P1 = lds + SLOTS * N2, *P2 = P1 + N2;
+        FftTw<N2, false, C> twf;
         twf.load(g, P.rt);
-        for (int k2 = tid; k2 < N2; k2 += SMOL_WG) P1[k2] = cmk(0.0, 0.0);
+        for (int k2 = tid; k2 < N2; k2 += SMOL_WG) P1[k2] = czero<C>();
         for (int a0 = 0; a0 < P.R; a0 += AL_PER_ROUND) {
             const int na = min(AL_PER_ROUND, P.R - a0);
             // slot 2m holds rank a0+m row k1, slot 2m+1 its row N1-k1
@@ -249,8 +265,8 @@ struct PhaseB {
                 const int m = slot >> 1, which = slot & 1;
                 if (m < na && !(single && which)) {
                     const int krow = which ? k1p : k1;
-                    const cd *src = P.Z + ((int64_t)(a0 + m) << P.logL) + (int64_t)krow * N2;
-                    cd v[F::E];
+                    const C *src = (const C *)P.Z + ((int64_t)(a0 + m) << P.logL) + (int64_t)krow * N2;
+                    C v[F::E];
 #pragma unroll
                     for (int i = 0; i < F::E; ++i) v[i] = src[g + i * F::G];
                     wave_fft<N2, false>(v, rows + slot * N2, g, twf);
@@ -263,15 +279,11 @@ struct PhaseB {
             for (int k2 = tid; k2 < N2; k2 += SMOL_WG) {
                 // partner of (k1, k2) is (k1p, k2p)
                 const int k2p = (k1 == 0) ? ((N2 - k2) & (N2 - 1)) : (N2 - 1 - k2);
-                cd acc = P1[k2];
+                C acc = P1[k2];
                 for (int m = 0; m < na; ++m) {
-                    const cd a = rows[(2 * m) * N2 + k2];
-                    const cd b = rows[(2 * m + (single ? 0 : 1)) * N2 + k2p];
-                    // a^2 - conj(b)^2
-                    const double re = (a.x * a.x - a.y * a.y) - (b.x * b.x - b.y * b.y);
-                    const double im = 2.0 * (a.x * a.y + b.x * b.y);
-                    acc.x += re;
-                    acc.y += im;
+                    const C a = rows[(2 * m) * N2 + k2];
+                    const C b = rows[(2 * m + (single ? 0 : 1)) * N2 + k2p];
+                    acc = spec_term(acc, a, b);
                 }
                 P1[k2] = acc;
             }
@@ -279,8 +291,7 @@ struct PhaseB {
         }
         // divide by 4i: x / (4i) = (x.y, -x.x) / 4; partner row by conjugate reversal
         for (int k2 = tid; k2 < N2; k2 += SMOL_WG) {
-            const cd x = P1[k2];
-            const cd q = cmk(0.25 * x.y, -0.25 * x.x);
+            const C q = div4i(P1[k2]);
             P1[k2] = q;
             if (!single) P2[N2 - 1 - k2] = cconj(q);
         }
@@ -288,21 +299,21 @@ struct PhaseB {
         // inverse DFT over k2 of rows k1 (slot 0) and N1-k1 (slot 1)
         if (slot < (single ? 1 : 2)) {
             const int krow = slot ? k1p : k1;
-            FftTw<N2, true> twi;
+            FftTw<N2, true, C> twi;
             twi.load(g, P.rt);
-            cd t4[F::E];
+            C t4[F::E];
             step_twiddles<F::E, true>(P.rt, P.logL, (uint32_t)krow, g, F::G, t4);
-            const cd *src = slot ? P2 : P1;
-            cd v[F::E];
+            const C *src = slot ? P2 : P1;
+            C v[F::E];
 #pragma unroll
             for (int i = 0; i < F::E; ++i) v[i] = src[g + i * F::G];
             wave_fft<N2, true>(v, rows + slot * N2, g, twi);
-            cd *dst = P.Qp + (int64_t)krow * (N2 / 2);
+            C *dst = (C *)P.Qp + (int64_t)krow * (N2 / 2);
 #pragma unroll
             for (int i = 0; i < F::E / 2; ++i) {
-                const cd lo = cmul(v[i], t4[i]);
-                const cd hi = cmul(v[i + F::E / 2], t4[i + F::E / 2]);
-                dst[g + i * F::G] = cmk(lo.x - hi.y, lo.y + hi.x);  // lo + i*hi
+                const C lo = cmul(v[i], t4[i]);
+                const C hi = cmul(v[i + F::E / 2], t4[i + F::E / 2]);
+                dst[g + i * F::G] = cadd(lo, crot<true>(hi));  // lo + i*hi
             }
         }
     }
@@ -331,7 +342,7 @@ __device__ inline void finalize_reductions(const RhsPlanDev &P, int njobs)
 // Phase C
 // --------------------------------------------------------------------------
 
-template <int N1, int N2>
+template <int N1, int N2, class C>
 struct PhaseC {
     using F = FftShape<N1>;
     static constexpr int HALF = N2 / 2;
@@ -345,7 +356,7 @@ struct PhaseC {
     static constexpr int KMAX = 6;  // stage vectors an epilogue combines
     static constexpr int RPRE = 4;  // ranks whose U, V are prefetched
 
-    __device__ static void run(const RhsPlanDev &P, const Epi &ep, int unit, cd *lds)
+    __device__ static void run(const RhsPlanDev &P, const Epi &ep, int unit, C *lds)
     {
         __shared__ double sh[SMOL_WAVES * 16];
         const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
@@ -392,12 +403,13 @@ struct PhaseC {
         if (w == 0) {
             const int f = lane / F::G, g = lane % F::G;
             const int ac = unit * COLS + f;
-            FftTw<N1, true> tw;
+            FftTw<N1, true, C> tw;
             tw.load(g, P.rt);
-            cd v[F::E];
+            C v[F::E];
+            const C *Qp = (const C *)P.Qp;
 #pragma unroll
             for (int i = 0; i < F::E; ++i)
-                v[i] = f < COLS ? P.Qp[(int64_t)(g + i * F::G) * HALF + ac] : cmk(0.0, 0.0);
+                v[i] = f < COLS ? Qp[(int64_t)(g + i * F::G) * HALF + ac] : czero<C>();
             wave_fft<N1, true>(v, lds + f * N1, g, tw);
             wave_sync();
             if (f < COLS) {
@@ -418,8 +430,8 @@ struct PhaseC {
             if (qv[j] >= 0) {
                 const int e = tid + j * SMOL_WG;
                 const int b = e % (N1 / 2), hh = (e / (N1 / 2)) & 1, f = e / N1;
-                const cd val = lds[f * (N1 / 2) + b];
-                const double c = (hh ? val.y : val.x) * invL;
+                const C val = lds[f * (N1 / 2) + b];
+                const double c = (hh ? im_d(val) : re_d(val)) * invL;
                 double dsum = 0.0;
 #pragma unroll
                 for (int a = 0; a < RPRE; ++a)

@@ -27,32 +27,32 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
     return (b % 8) * (nb / 8) + b / 8;
 }
 
-template <int N1, int N2>
+template <int N1, int N2, class T>
 __global__ __launch_bounds__(SMOL_WG) void k_phaseA(RhsPlanDev P, Pro in, int nunits)
 {
     extern __shared__ cd lds[];
     const int unit = xcd_remap(blockIdx.x, gridDim.x);
-    if (unit < nunits) PhaseA<N1, N2>::run(P, in, unit, lds);
+    if (unit < nunits) PhaseA<N1, N2, T>::run(P, in, unit, (T *)lds);
 }
 
-template <int N1, int N2>
+template <int N1, int N2, class T>
 __global__ __launch_bounds__(SMOL_WG) void k_phaseB(RhsPlanDev P, int red_jobs)
 {
     extern __shared__ cd lds[];
     const int u = blockIdx.x;
-    if (u == PhaseB<N1, N2>::units()) {
+    if (u == PhaseB<N1, N2, T>::units()) {
         if (red_jobs > 0) finalize_reductions(P, red_jobs);
         return;
     }
-    PhaseB<N1, N2>::run(P, u, lds);
+    PhaseB<N1, N2, T>::run(P, u, (T *)lds);
 }
 
-template <int N1, int N2>
+template <int N1, int N2, class T>
 __global__ __launch_bounds__(SMOL_WG) void k_phaseC(RhsPlanDev P, Epi ep, int nunits)
 {
     extern __shared__ cd lds[];
     const int unit = xcd_remap(blockIdx.x, gridDim.x);
-    if (unit < nunits) PhaseC<N1, N2>::run(P, ep, unit, lds);
+    if (unit < nunits) PhaseC<N1, N2, T>::run(P, ep, unit, (T *)lds);
 }
 
 // Layout conversion of `rows` vectors of M sizes: natural <-> transposed.
@@ -77,20 +77,20 @@ __global__ void k_from_tr(const double *src, double *dst, int64_t M, int logL)
 // Integration kernels: the same phases, buffers chosen from the control block
 // --------------------------------------------------------------------------
 
-template <int N1, int N2>
+template <int N1, int N2, class T>
 __global__ __launch_bounds__(SMOL_WG) void k_int_A(IntegDev I, int stage, int nunits)
 {
     const IntegCtl &c = *I.ctl;
     if (c.done) return;
     extern __shared__ cd lds[];
-    const Tableau &T = c_tab[c.method];
+    const Tableau &tab = c_tab[c.method];
     const RhsPlanDev P = plan_of(I, c);
-    const Pro in = stage_pro(I, c, T, stage);
+    const Pro in = stage_pro(I, c, tab, stage);
     const int unit = xcd_remap(blockIdx.x, gridDim.x);
-    if (unit < nunits) PhaseA<N1, N2>::run(P, in, unit, lds);
+    if (unit < nunits) PhaseA<N1, N2, T>::run(P, in, unit, (T *)lds);
 }
 
-template <int N1, int N2>
+template <int N1, int N2, class T>
 __global__ __launch_bounds__(SMOL_WG) void k_int_B(IntegDev I, int stage)
 {
     const IntegCtl &c = *I.ctl;
@@ -98,25 +98,25 @@ __global__ __launch_bounds__(SMOL_WG) void k_int_B(IntegDev I, int stage)
     extern __shared__ cd lds[];
     const RhsPlanDev P = plan_of(I, c);
     const int u = blockIdx.x;
-    if (u == PhaseB<N1, N2>::units()) {
+    if (u == PhaseB<N1, N2, T>::units()) {
         // partials of y come from phase A (stages 0..2) or the previous finish
-        finalize_reductions(P, stage <= 2 ? PhaseA<N1, N2>::red_jobs() : PhaseC<N1, N2>::units());
+        finalize_reductions(P, stage <= 2 ? PhaseA<N1, N2, T>::red_jobs() : PhaseC<N1, N2, T>::units());
         return;
     }
-    PhaseB<N1, N2>::run(P, u, lds);
+    PhaseB<N1, N2, T>::run(P, u, (T *)lds);
 }
 
-template <int N1, int N2>
+template <int N1, int N2, class T>
 __global__ __launch_bounds__(SMOL_WG) void k_int_C(IntegDev I, int stage, int nunits)
 {
     const IntegCtl &c = *I.ctl;
     if (c.done) return;
     extern __shared__ cd lds[];
-    const Tableau &T = c_tab[c.method];
+    const Tableau &tab = c_tab[c.method];
     const RhsPlanDev P = plan_of(I, c);
-    const Epi ep = stage_epi(I, c, T, stage);
+    const Epi ep = stage_epi(I, c, tab, stage);
     const int unit = xcd_remap(blockIdx.x, gridDim.x);
-    if (unit < nunits) PhaseC<N1, N2>::run(P, ep, unit, lds);
+    if (unit < nunits) PhaseC<N1, N2, T>::run(P, ep, unit, (T *)lds);
 }
 
 // Deterministic block reduction of epart rows (fixed strided order, then a
@@ -285,7 +285,7 @@ struct Plan {
     int64_t M = 0;
     int R = 0, precision = 0;
     int logL = 0, logN1 = 0, logN2 = 0;
-    cd *Z = nullptr, *Qp = nullptr;
+    cd *Z = nullptr, *Qp = nullptr;  // cd or cff storage (16 B per complex either way)
     double *red_part = nullptr, *red = nullptr, *epart = nullptr;
     // integration state (allocated on first use)
     int64_t Mt = 0;                // vector length in the transposed layout
@@ -412,29 +412,35 @@ RhsPlanDev dev_plan(const Plan *p, const DevRoots *r, const double *U, const dou
 }
 
 // Launch phases A, B, C for one right-hand side.
-template <int N1, int N2>
+template <int N1, int N2, class T>
 int launch_rhs_t(const RhsPlanDev &P, const Pro &in, const Epi &ep, hipStream_t s)
 {
-    using A = PhaseA<N1, N2>;
-    using B = PhaseB<N1, N2>;
-    using C = PhaseC<N1, N2>;
+    using A = PhaseA<N1, N2, T>;
+    using B = PhaseB<N1, N2, T>;
+    using C = PhaseC<N1, N2, T>;
     const int nA = A::units(P.R), nC = C::units();
-    hipLaunchKernelGGL((k_phaseA<N1, N2>), dim3(nA), dim3(SMOL_WG), sizeof(cd) * A::LDS, s, P,
+    hipLaunchKernelGGL((k_phaseA<N1, N2, T>), dim3(nA), dim3(SMOL_WG), sizeof(cd) * A::LDS, s, P,
                        in, nA);
     const int redj = (in.mode == A_COMBINE) ? A::red_jobs() : 0;
-    hipLaunchKernelGGL((k_phaseB<N1, N2>), dim3(B::units() + 1), dim3(SMOL_WG),
+    hipLaunchKernelGGL((k_phaseB<N1, N2, T>), dim3(B::units() + 1), dim3(SMOL_WG),
                        sizeof(cd) * B::LDS, s, P, redj);
-    hipLaunchKernelGGL((k_phaseC<N1, N2>), dim3(nC), dim3(SMOL_WG), sizeof(cd) * C::LDS, s, P,
+    hipLaunchKernelGGL((k_phaseC<N1, N2, T>), dim3(nC), dim3(SMOL_WG), sizeof(cd) * C::LDS, s, P,
                        ep, nC);
     HIP_TRY(hipGetLastError());
     return SMOL_OK;
 }
 
-int launch_rhs(const RhsPlanDev &P, const Pro &in, const Epi &ep, hipStream_t s)
+// Call F::template run<N1, N2, T>(args...) for the transform shape of logL
+// and the complex arithmetic of `precision` (cd: FP64, cff: float-float).
+template <class F, class... Args>
+int with_shape(int logL, int precision, Args &&...args)
 {
-    switch (P.logL) {
-#define CASE(LL, A, B) \
-    case LL: return launch_rhs_t<(1 << A), (1 << B)>(P, in, ep, s);
+    switch (logL) {
+#define CASE(LL, A, B)                                                        \
+    case LL:                                                                  \
+        return precision == SMOL_FP32X2                                       \
+                   ? F::template run<(1 << A), (1 << B), cff>(args...)        \
+                   : F::template run<(1 << A), (1 << B), cd>(args...);
         CASE(6, 3, 3)
         CASE(7, 4, 3)
         CASE(8, 4, 4)
@@ -455,47 +461,28 @@ int launch_rhs(const RhsPlanDev &P, const Pro &in, const Epi &ep, hipStream_t s)
     }
 }
 
-// Call F::template run<N1, N2>(args...) for the plan's transform shape.
-template <class F, class... Args>
-int with_shape(int logL, Args &&...args)
-{
-    switch (logL) {
-#define CASE(LL, A, B) \
-    case LL: return F::template run<(1 << A), (1 << B)>(args...);
-        CASE(6, 3, 3)
-        CASE(7, 4, 3)
-        CASE(8, 4, 4)
-        CASE(9, 5, 4)
-        CASE(10, 5, 5)
-        CASE(11, 6, 5)
-        CASE(12, 6, 6)
-        CASE(13, 7, 6)
-        CASE(14, 7, 7)
-        CASE(15, 8, 7)
-        CASE(16, 8, 8)
-        CASE(17, 9, 8)
-        CASE(18, 9, 9)
-        CASE(19, 10, 9)
-        CASE(20, 10, 10)
-#undef CASE
-    default: return SMOL_EUNSUPPORTED;
+struct LaunchRhs {
+    template <int N1, int N2, class T>
+    static int run(const RhsPlanDev &P, const Pro &in, const Epi &ep, hipStream_t s)
+    {
+        return launch_rhs_t<N1, N2, T>(P, in, ep, s);
     }
-}
+};
 
 // One stage (or starting-step evaluation) of the integrator: A, B, C.
 struct LaunchStage {
-    template <int N1, int N2>
+    template <int N1, int N2, class T>
     static int run(const IntegDev &I, int stage, hipStream_t s)
     {
-        using A = PhaseA<N1, N2>;
-        using B = PhaseB<N1, N2>;
-        using C = PhaseC<N1, N2>;
+        using A = PhaseA<N1, N2, T>;
+        using B = PhaseB<N1, N2, T>;
+        using C = PhaseC<N1, N2, T>;
         const int nA = A::units(I.R), nC = C::units();
-        hipLaunchKernelGGL((k_int_A<N1, N2>), dim3(nA), dim3(SMOL_WG), sizeof(cd) * A::LDS, s, I,
+        hipLaunchKernelGGL((k_int_A<N1, N2, T>), dim3(nA), dim3(SMOL_WG), sizeof(cd) * A::LDS, s, I,
                            stage, nA);
-        hipLaunchKernelGGL((k_int_B<N1, N2>), dim3(B::units() + 1), dim3(SMOL_WG),
+        hipLaunchKernelGGL((k_int_B<N1, N2, T>), dim3(B::units() + 1), dim3(SMOL_WG),
                            sizeof(cd) * B::LDS, s, I, stage);
-        hipLaunchKernelGGL((k_int_C<N1, N2>), dim3(nC), dim3(SMOL_WG), sizeof(cd) * C::LDS, s, I,
+        hipLaunchKernelGGL((k_int_C<N1, N2, T>), dim3(nC), dim3(SMOL_WG), sizeof(cd) * C::LDS, s, I,
                            stage, nC);
         HIP_TRY(hipGetLastError());
         return SMOL_OK;
@@ -503,10 +490,10 @@ struct LaunchStage {
 };
 
 struct PhaseCJobs {
-    template <int N1, int N2>
+    template <int N1, int N2, class T>
     static int run()
     {
-        return PhaseC<N1, N2>::units();
+        return PhaseC<N1, N2, T>::units();
     }
 };
 
@@ -561,10 +548,10 @@ int get_step_graph(Plan *p, const IntegDev &I, int method, hipGraphExec_t *out)
     hipGraph_t g;
     HIP_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
     int rc = SMOL_OK;
-    const int nC = with_shape<PhaseCJobs>(p->logL);
+    const int nC = with_shape<PhaseCJobs>(p->logL, SMOL_FP64);
     for (int a = 0; a < SMOL_GRAPH_ATTEMPTS; ++a) {
         for (int st = 2; st <= S && rc == SMOL_OK; ++st)
-            rc = with_shape<LaunchStage>(p->logL, I, st, p->cap);
+            rc = with_shape<LaunchStage>(p->logL, p->precision, I, st, p->cap);
         hipLaunchKernelGGL(k_ctrl, dim3(1), dim3(SMOL_WG), 0, p->cap, I, nC);
     }
     hipError_t e = hipStreamEndCapture(p->cap, &g);
@@ -611,7 +598,6 @@ extern "C" int smol_rhs(int64_t M, int32_t R, const double *U, const double *V, 
     if (rc) return rc;
     if (!n || !dndt || n == dndt) return SMOL_EINVAL;
     if (precision != SMOL_FP64 && precision != SMOL_FP32X2) return SMOL_EINVAL;
-    if (precision != SMOL_FP64) return SMOL_EUNSUPPORTED;
     std::lock_guard<std::mutex> lk(g_mu);
     Plan *p;
     DevRoots *r;
@@ -623,7 +609,7 @@ extern "C" int smol_rhs(int64_t M, int32_t R, const double *U, const double *V, 
     ep.mode = C_RHS;
     ep.y = n;
     ep.out = dndt;
-    return launch_rhs(P, in, ep, (hipStream_t)stream);
+    return with_shape<LaunchRhs>(p->logL, precision, P, in, ep, (hipStream_t)stream);
 }
 
 extern "C" int smol_release_plans(void)
@@ -677,7 +663,7 @@ extern "C" int smol_integrate_ex(int64_t M, int32_t R, const double *U, const do
     if (opts) o = *opts;
     if (o.h0 < 0 || o.h_min < 0 || o.max_steps < 0 || (o.log && o.log_cap < 0)) return SMOL_EINVAL;
     if (o.controller != SMOL_CTRL_PI && o.controller != SMOL_CTRL_LEARNED) return SMOL_EINVAL;
-    if (precision != SMOL_FP64 || o.controller != SMOL_CTRL_PI) return SMOL_EUNSUPPORTED;
+    if (o.controller != SMOL_CTRL_PI) return SMOL_EUNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     if (stats) memset(stats, 0, sizeof(*stats));
     if (t_end == 0.0) {
@@ -726,12 +712,12 @@ extern "C" int smol_integrate_ex(int64_t M, int32_t R, const double *U, const do
     hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, U, I.Ut, M, R, M, I.Mt, p->logL);
     hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, V, I.Vt, M, R, M, I.Mt, p->logL);
     hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, n0, I.nb[0], M, 1, M, I.Mt, p->logL);
-    const int nC = with_shape<PhaseCJobs>(p->logL);
+    const int nC = with_shape<PhaseCJobs>(p->logL, SMOL_FP64);
     // starting step: S(n0), h0, S(n0 + h0 f0), h
-    if ((rc = with_shape<LaunchStage>(p->logL, I, 0, s))) return rc;
+    if ((rc = with_shape<LaunchStage>(p->logL, p->precision, I, 0, s))) return rc;
     hipLaunchKernelGGL(k_init_h0, dim3(1), dim3(SMOL_WG), 0, s, I, nC);
     if (!(o.h0 > 0)) {
-        if ((rc = with_shape<LaunchStage>(p->logL, I, 1, s))) return rc;
+        if ((rc = with_shape<LaunchStage>(p->logL, p->precision, I, 1, s))) return rc;
         hipLaunchKernelGGL(k_init_h, dim3(1), dim3(SMOL_WG), 0, s, I, nC);
     }
     HIP_TRY(hipGetLastError());
@@ -769,31 +755,31 @@ extern "C" int smol_integrate(int64_t M, int32_t R, const double *U, const doubl
 
 namespace {
 struct ProfileRhs {
-    template <int N1, int N2>
+    template <int N1, int N2, class T>
     static int run(const RhsPlanDev &P, const Pro &in, const Epi &ep, int iters, float *ms,
                    hipStream_t s)
     {
-        using A = PhaseA<N1, N2>;
-        using B = PhaseB<N1, N2>;
-        using C = PhaseC<N1, N2>;
+        using A = PhaseA<N1, N2, T>;
+        using B = PhaseB<N1, N2, T>;
+        using C = PhaseC<N1, N2, T>;
         const int nA = A::units(P.R), nC = C::units();
         hipEvent_t ev[5];
         for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
         HIP_TRY(hipEventRecord(ev[0], s));
         for (int i = 0; i < iters; ++i)
-            hipLaunchKernelGGL((k_phaseA<N1, N2>), dim3(nA), dim3(SMOL_WG), sizeof(cd) * A::LDS, s,
+            hipLaunchKernelGGL((k_phaseA<N1, N2, T>), dim3(nA), dim3(SMOL_WG), sizeof(cd) * A::LDS, s,
                                P, in, nA);
         HIP_TRY(hipEventRecord(ev[1], s));
         for (int i = 0; i < iters; ++i)
-            hipLaunchKernelGGL((k_phaseB<N1, N2>), dim3(B::units() + 1), dim3(SMOL_WG),
+            hipLaunchKernelGGL((k_phaseB<N1, N2, T>), dim3(B::units() + 1), dim3(SMOL_WG),
                                sizeof(cd) * B::LDS, s, P, A::red_jobs());
         HIP_TRY(hipEventRecord(ev[2], s));
         for (int i = 0; i < iters; ++i)
-            hipLaunchKernelGGL((k_phaseC<N1, N2>), dim3(nC), dim3(SMOL_WG), sizeof(cd) * C::LDS, s,
+            hipLaunchKernelGGL((k_phaseC<N1, N2, T>), dim3(nC), dim3(SMOL_WG), sizeof(cd) * C::LDS, s,
                                P, ep, nC);
         HIP_TRY(hipEventRecord(ev[3], s));
         for (int i = 0; i < iters; ++i) {
-            int rc = launch_rhs_t<N1, N2>(P, in, ep, s);
+            int rc = launch_rhs_t<N1, N2, T>(P, in, ep, s);
             if (rc) return rc;
         }
         HIP_TRY(hipEventRecord(ev[4], s));
@@ -836,7 +822,7 @@ extern "C" int smol_profile_rhs(int64_t M, int32_t R, const double *U, const dou
     ep.mode = C_RHS;
     ep.y = I.nb[0];
     ep.out = I.kslot[0];
-    rc = with_shape<ProfileRhs>(p->logL, P, in, ep, iters, ms_out, s);
+    rc = with_shape<ProfileRhs>(p->logL, SMOL_FP64, P, in, ep, iters, ms_out, s);
     if (rc) return rc;
     hipLaunchKernelGGL(k_from_tr, dim3(256), dim3(256), 0, s, I.kslot[0], dndt, M, p->logL);
     HIP_TRY(hipGetLastError());
