@@ -1,0 +1,379 @@
+// Batched integration of many independent instances (uneven M, kernels,
+// lambda and tolerances), each with its own step size, accept / reject and
+// status.  Every kernel of a step attempt is ONE launch over all instances:
+// a block-to-instance table gives each workgroup its instance and unit, a
+// switch selects the instance's transform shape, and per-instance control
+// blocks carry the state, so the attempt is captured once as a hipGraph and
+// replayed until every instance is done (finished instances' workgroups
+// return at entry).  With hundreds of instances each launch holds tens of
+// thousands of workgroups, which fills the chip and hides memory latency
+// that a single small instance cannot.
+#include <cstring>
+#include <vector>
+
+#include "host.h"
+
+struct BatchDev {
+    const IntegDev *inst;   // per instance
+    const int *logL;        // per instance
+    const int *first[3];    // first block of each instance per kernel A, B, C
+    const int *owner[3];    // instance of each block per kernel
+    const int *nC;          // finish units per instance
+    const int *redA;        // column-pass reduction jobs per instance
+};
+
+#define SMOL_SHAPES(X) \
+    X(6, 3, 3) X(7, 4, 3) X(8, 4, 4) X(9, 5, 4) X(10, 5, 5) X(11, 6, 5) X(12, 6, 6) X(13, 7, 6) \
+    X(14, 7, 7) X(15, 8, 7) X(16, 8, 8) X(17, 9, 8) X(18, 9, 9) X(19, 10, 9) X(20, 10, 10)
+
+template <class T>
+__global__ __launch_bounds__(SMOL_WG) void kb_A(BatchDev B, int stage)
+{
+    extern __shared__ cd lds[];
+    const int b = B.owner[0][blockIdx.x];
+    const IntegDev &I = B.inst[b];
+    const IntegCtl &c = *I.ctl;
+    if (c.done) return;
+    const RhsPlanDev P = plan_of(I, c);
+    const Pro in = stage_pro(I, c, c_tab[c.method], stage);
+    const int unit = blockIdx.x - B.first[0][b];
+    switch (B.logL[b]) {
+#define X(LL, A, Bb) \
+    case LL: PhaseA<(1 << A), (1 << Bb), T>::run(P, in, unit, (T *)lds); break;
+        SMOL_SHAPES(X)
+#undef X
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(SMOL_WG) void kb_B(BatchDev B, int stage)
+{
+    extern __shared__ cd lds[];
+    const int b = B.owner[1][blockIdx.x];
+    const IntegDev &I = B.inst[b];
+    const IntegCtl &c = *I.ctl;
+    if (c.done) return;
+    const RhsPlanDev P = plan_of(I, c);
+    const int unit = blockIdx.x - B.first[1][b];
+    const int logL = B.logL[b];
+    if (unit == (1 << ((logL + 1) / 2 - 1)) + 1) {  // N1/2 + 1: the finaliser
+        finalize_reductions(P, stage <= 2 ? B.redA[b] : B.nC[b]);
+        return;
+    }
+    switch (logL) {
+#define X(LL, A, Bb) \
+    case LL: PhaseB<(1 << A), (1 << Bb), T>::run(P, unit, (T *)lds); break;
+        SMOL_SHAPES(X)
+#undef X
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(SMOL_WG) void kb_C(BatchDev B, int stage)
+{
+    extern __shared__ cd lds[];
+    const int b = B.owner[2][blockIdx.x];
+    const IntegDev &I = B.inst[b];
+    const IntegCtl &c = *I.ctl;
+    if (c.done) return;
+    const RhsPlanDev P = plan_of(I, c);
+    const Epi ep = stage_epi(I, c, c_tab[c.method], stage);
+    const int unit = blockIdx.x - B.first[2][b];
+    switch (B.logL[b]) {
+#define X(LL, A, Bb) \
+    case LL: PhaseC<(1 << A), (1 << Bb), T>::run(P, ep, unit, (T *)lds); break;
+        SMOL_SHAPES(X)
+#undef X
+    }
+}
+
+// one workgroup per instance
+__global__ __launch_bounds__(SMOL_WG) void kb_init_h0(BatchDev B)
+{
+    init_h0_step(B.inst[blockIdx.x], B.nC[blockIdx.x]);
+}
+__global__ __launch_bounds__(SMOL_WG) void kb_init_h(BatchDev B)
+{
+    init_h_step(B.inst[blockIdx.x], B.nC[blockIdx.x]);
+}
+__global__ __launch_bounds__(SMOL_WG) void kb_ctrl(BatchDev B)
+{
+    controller_step(B.inst[blockIdx.x], B.nC[blockIdx.x]);
+}
+
+namespace {
+
+struct BatchRun {
+    int n = 0, R_max = 0;
+    std::vector<int> logL, units[3], red, ldsmax;
+    std::vector<size_t> off;     // arena offset of each instance
+    size_t arena_bytes = 0;
+    int total[3] = {0, 0, 0};
+    size_t lds[3] = {0, 0, 0};
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+template <class T>
+void launch_stage(const BatchDev &B, const BatchRun &br, int stage, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_A<T>, dim3(br.total[0]), dim3(SMOL_WG), br.lds[0], s, B, stage);
+    hipLaunchKernelGGL(kb_B<T>, dim3(br.total[1]), dim3(SMOL_WG), br.lds[1], s, B, stage);
+    hipLaunchKernelGGL(kb_C<T>, dim3(br.total[2]), dim3(SMOL_WG), br.lds[2], s, B, stage);
+}
+
+void launch_stage_p(int precision, const BatchDev &B, const BatchRun &br, int stage, hipStream_t s)
+{
+    if (precision == SMOL_FP32X2)
+        launch_stage<cff>(B, br, stage, s);
+    else
+        launch_stage<cd>(B, br, stage, s);
+}
+
+}  // namespace
+
+extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, int32_t method,
+                                    int32_t precision, const smol_options *opts,
+                                    smol_stats *stats, void *stream)
+{
+    if (n_inst < 1 || !inst || !stats) return SMOL_EINVAL;
+    if (method != SMOL_BS32 && method != SMOL_DP54) return SMOL_EINVAL;
+    if (precision != SMOL_FP64 && precision != SMOL_FP32X2) return SMOL_EINVAL;
+    smol_options o{};
+    if (opts) o = *opts;
+    if (o.h0 < 0 || o.h_min < 0 || o.max_steps < 0 || o.log) return SMOL_EINVAL;
+    if (o.controller != SMOL_CTRL_PI && o.controller != SMOL_CTRL_LEARNED) return SMOL_EINVAL;
+    if (o.controller != SMOL_CTRL_PI) return SMOL_EUNSUPPORTED;
+    for (int i = 0; i < n_inst; ++i) {
+        const smol_instance &q = inst[i];
+        int rc = check_common(q.M, q.R, q.U, q.V, q.lambda);
+        if (rc) return rc;
+        if (!q.n0 || !q.n_out) return SMOL_EINVAL;
+        if (!(q.rtol > 0) || !(q.atol >= 0) || !(q.t_end >= 0) || !std::isfinite(q.t_end))
+            return SMOL_EINVAL;
+    }
+    memset(stats, 0, sizeof(smol_stats) * n_inst);
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lk(g_mu);
+    int dev;
+    HIP_TRY(hipGetDevice(&dev));
+    DevRoots *roots;
+    int rc = get_roots(dev, &roots);
+    if (rc) return rc;
+
+    // ---- sizes, block tables and arena layout
+    BatchRun br;
+    br.n = n_inst;
+    std::vector<int> first[3], owner[3], nC(n_inst), redA(n_inst);
+    for (int k = 0; k < 3; ++k) first[k].resize(n_inst + 1);
+    br.logL.resize(n_inst);
+    br.off.resize(n_inst);
+    size_t at = 0;
+    const size_t ctl_bytes = align256(sizeof(IntegCtl) * n_inst);
+    at = ctl_bytes;
+    for (int i = 0; i < n_inst; ++i) {
+        const smol_instance &q = inst[i];
+        const int logL = fft_log2(q.M);
+        br.logL[i] = logL;
+        int u[8];
+        if ((rc = with_shape<ShapeUnits>(logL, precision, (int)q.R, u))) return rc;
+        for (int k = 0; k < 3; ++k) {
+            first[k][i] = br.total[k];
+            for (int j = 0; j < u[k]; ++j) owner[k].push_back(i);
+            br.total[k] += u[k];
+            const size_t lb = sizeof(cd) * (size_t)u[4 + k];
+            if (lb > br.lds[k]) br.lds[k] = lb;
+        }
+        nC[i] = u[2];
+        redA[i] = u[3];
+        const int64_t L = 1LL << logL, half = L / 2, N2 = 1LL << (logL / 2);
+        const int64_t Mt = q.M > half + 1 ? q.M : half + 1;
+        br.off[i] = at;
+        at += align256(sizeof(double) * (size_t)Mt * 10);                 // state, stages
+        at += align256(sizeof(double) * (size_t)Mt * 2 * q.R);            // U, V copies
+        at += align256(sizeof(cd) * (size_t)(q.R * L + L / 2));           // spectra
+        at += align256(sizeof(double) * (size_t)(N2 * q.R * 4 + 4 * q.R + N2 * SMOL_EPART));
+    }
+    for (int k = 0; k < 3; ++k) first[k][n_inst] = br.total[k];
+    const size_t tab_off = at;
+    size_t tab_bytes = 0;
+    tab_bytes += align256(sizeof(IntegDev) * n_inst);
+    tab_bytes += align256(sizeof(int) * n_inst) * 3;  // logL, nC, redA
+    for (int k = 0; k < 3; ++k)
+        tab_bytes += align256(sizeof(int) * (n_inst + 1)) + align256(sizeof(int) * br.total[k]);
+    br.arena_bytes = at + tab_bytes;
+
+    char *arena = nullptr;
+    if (hipMalloc(&arena, br.arena_bytes) != hipSuccess) return SMOL_ENOMEM;
+    IntegCtl *hctl = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t ge = nullptr;
+    rc = SMOL_OK;
+    do {
+        if (hipHostMalloc(&hctl, sizeof(IntegCtl) * n_inst, hipHostMallocDefault) != hipSuccess) {
+            rc = SMOL_ENOMEM;
+            break;
+        }
+        // ---- per-instance device views and control blocks
+        IntegCtl *dctl = (IntegCtl *)arena;
+        std::vector<IntegDev> hdev(n_inst);
+        const int kq = (method == SMOL_DP54 ? 4 : 2) + 1;
+        for (int i = 0; i < n_inst; ++i) {
+            const smol_instance &q = inst[i];
+            const int logL = br.logL[i];
+            const int64_t L = 1LL << logL, half = L / 2, N2 = 1LL << (logL / 2);
+            const int64_t Mt = q.M > half + 1 ? q.M : half + 1;
+            char *p = arena + br.off[i];
+            double *ibuf = (double *)p;
+            p += align256(sizeof(double) * (size_t)Mt * 10);
+            double *uvt = (double *)p;
+            p += align256(sizeof(double) * (size_t)Mt * 2 * q.R);
+            cd *Z = (cd *)p;
+            p += align256(sizeof(cd) * (size_t)(q.R * L + L / 2));
+            double *red_part = (double *)p;
+            IntegDev &I = hdev[i];
+            memset(&I, 0, sizeof(I));
+            I.M = q.M;
+            I.Mt = Mt;
+            I.R = q.R;
+            I.logL = logL;
+            I.Ut = uvt;
+            I.Vt = uvt + (size_t)q.R * Mt;
+            I.ctl = dctl + i;
+            I.nb[0] = ibuf;
+            I.nb[1] = ibuf + Mt;
+            for (int j = 0; j < 7; ++j) I.kslot[j] = ibuf + (2 + j) * Mt;
+            I.ybuf = ibuf + 9 * Mt;
+            I.Z = Z;
+            I.Qp = Z + q.R * L;
+            I.red_part = red_part;
+            I.red = red_part + (size_t)N2 * q.R * 4;
+            I.epart = I.red + (size_t)q.R * 4;
+            I.rt.tw = roots->tw;
+            I.rt.fine = roots->fine;
+            IntegCtl &c = hctl[i];
+            memset(&c, 0, sizeof(c));
+            c.U = I.Ut;
+            c.V = I.Vt;
+            c.lam = q.lambda;
+            c.t_end = q.t_end;
+            c.rtol = q.rtol;
+            c.atol = q.atol;
+            c.h_min = o.h_min;
+            c.h0_user = o.h0;
+            c.alpha = o.alpha > 0 ? o.alpha : 0.7 / kq;
+            c.beta = o.alpha > 0 ? o.beta : 0.4 / kq;
+            c.safety = 0.9;
+            c.facmin = 0.2;
+            c.facmax = 10.0;
+            c.max_steps = o.max_steps > 0 ? o.max_steps : 100000000LL;
+            c.method = method;
+            c.controller = o.controller;
+            c.err_prev = 1.0;
+            c.done = q.t_end == 0.0;  // nothing to do: n_out = n0
+        }
+        // ---- tables
+        char *tp = arena + tab_off;
+        auto put = [&](const void *src, size_t bytes) -> char * {
+            char *d = tp;
+            tp += align256(bytes);
+            return (hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, s) == hipSuccess) ? d : nullptr;
+        };
+        BatchDev B;
+        B.inst = (const IntegDev *)put(hdev.data(), sizeof(IntegDev) * n_inst);
+        B.logL = (const int *)put(br.logL.data(), sizeof(int) * n_inst);
+        B.nC = (const int *)put(nC.data(), sizeof(int) * n_inst);
+        B.redA = (const int *)put(redA.data(), sizeof(int) * n_inst);
+        for (int k = 0; k < 3; ++k) {
+            B.first[k] = (const int *)put(first[k].data(), sizeof(int) * (n_inst + 1));
+            B.owner[k] = (const int *)put(owner[k].data(), sizeof(int) * br.total[k]);
+        }
+        if (hipMemcpyAsync(dctl, hctl, sizeof(IntegCtl) * n_inst, hipMemcpyHostToDevice, s) != hipSuccess) {
+            rc = SMOL_EDEVICE;
+            break;
+        }
+        // ---- inputs into the transposed layout
+        for (int i = 0; i < n_inst; ++i) {
+            const smol_instance &q = inst[i];
+            const IntegDev &I = hdev[i];
+            hipLaunchKernelGGL(k_to_tr, dim3(128), dim3(256), 0, s, q.U, I.Ut, q.M, q.R, q.M, I.Mt, I.logL);
+            hipLaunchKernelGGL(k_to_tr, dim3(128), dim3(256), 0, s, q.V, I.Vt, q.M, q.R, q.M, I.Mt, I.logL);
+            hipLaunchKernelGGL(k_to_tr, dim3(128), dim3(256), 0, s, q.n0, I.nb[0], q.M, 1, q.M, I.Mt, I.logL);
+        }
+        // ---- starting step for every instance
+        launch_stage_p(precision, B, br, 0, s);
+        hipLaunchKernelGGL(kb_init_h0, dim3(n_inst), dim3(SMOL_WG), 0, s, B);
+        if (!(o.h0 > 0)) {
+            launch_stage_p(precision, B, br, 1, s);
+            hipLaunchKernelGGL(kb_init_h, dim3(n_inst), dim3(SMOL_WG), 0, s, B);
+        }
+        if (hipGetLastError() != hipSuccess) {
+            rc = SMOL_EDEVICE;
+            break;
+        }
+        // ---- graph of SMOL_GRAPH_ATTEMPTS attempts for all instances
+        if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+            rc = SMOL_EDEVICE;
+            break;
+        }
+        const int S = method == SMOL_DP54 ? 7 : 4;
+        hipGraph_t g;
+        if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            rc = SMOL_EDEVICE;
+            break;
+        }
+        for (int a = 0; a < SMOL_GRAPH_ATTEMPTS; ++a) {
+            for (int st = 2; st <= S; ++st) launch_stage_p(precision, B, br, st, cap);
+            hipLaunchKernelGGL(kb_ctrl, dim3(n_inst), dim3(SMOL_WG), 0, cap, B);
+        }
+        if (hipStreamEndCapture(cap, &g) != hipSuccess) {
+            rc = SMOL_EDEVICE;
+            break;
+        }
+        hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            rc = SMOL_EDEVICE;
+            break;
+        }
+        // ---- replay until every instance is done
+        int64_t chunk = 1;
+        for (;;) {
+            for (int64_t k = 0; k < chunk && rc == SMOL_OK; ++k)
+                if (hipGraphLaunch(ge, s) != hipSuccess) rc = SMOL_EDEVICE;
+            if (rc) break;
+            if (hipMemcpyAsync(hctl, dctl, sizeof(IntegCtl) * n_inst, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                rc = SMOL_EDEVICE;
+                break;
+            }
+            double most = 0.0;
+            bool all = true;
+            for (int i = 0; i < n_inst; ++i) {
+                if (hctl[i].done) continue;
+                all = false;
+                double est = hctl[i].h > 0 ? (hctl[i].t_end - hctl[i].t) / hctl[i].h : 1e9;
+                if (!(est < 1e9)) est = 1e9;
+                if (est > most) most = est;
+            }
+            if (all) break;
+            chunk = (int64_t)(0.8 * most / SMOL_GRAPH_ATTEMPTS) + 1;
+            if (chunk > 64) chunk = 64;
+        }
+        if (rc) break;
+        // ---- outputs
+        for (int i = 0; i < n_inst; ++i) {
+            const IntegDev &I = hdev[i];
+            hipLaunchKernelGGL(k_from_tr, dim3(128), dim3(256), 0, s, I.nb[hctl[i].cur], inst[i].n_out,
+                               inst[i].M, I.logL);
+            stats_from(hctl[i], &stats[i]);
+        }
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) rc = SMOL_EDEVICE;
+    } while (0);
+    if (ge) (void)hipGraphExecDestroy(ge);
+    if (cap) (void)hipStreamDestroy(cap);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(arena);
+    if (hctl) (void)hipHostFree(hctl);
+    return rc;
+}

@@ -189,10 +189,144 @@ __device__ inline void prepare_attempt(IntegCtl &c, bool new_step)
     c.h = tn - c.t;
 }
 
-// Sum njobs partial rows of SMOL_EPART doubles in job order (one thread).
-__device__ inline void sum_epart(const double *ep, int njobs, double *acc)
+// Deterministic block reduction of epart rows (fixed strided order, then a
+// fixed tree); thread 0 receives the totals.
+__device__ inline void block_sum_epart(const double *ep, int njobs, double *tot)
 {
+    __shared__ double sh[SMOL_WG][SMOL_EPART];
+    const int tid = threadIdx.x;
+    double acc[SMOL_EPART];
     for (int q = 0; q < SMOL_EPART; ++q) acc[q] = 0.0;
-    for (int j = 0; j < njobs; ++j)
+    for (int j = tid; j < njobs; j += SMOL_WG)
         for (int q = 0; q < SMOL_EPART; ++q) acc[q] += ep[(int64_t)j * SMOL_EPART + q];
+    for (int q = 0; q < SMOL_EPART; ++q) sh[tid][q] = acc[q];
+    __syncthreads();
+    for (int off = SMOL_WG / 2; off >= 1; off >>= 1) {
+        if (tid < off)
+            for (int q = 0; q < SMOL_EPART; ++q) sh[tid][q] += sh[tid + off][q];
+        __syncthreads();
+    }
+    if (tid == 0)
+        for (int q = 0; q < SMOL_EPART; ++q) tot[q] = sh[0][q];
+}
+
+__device__ __forceinline__ double rms_of(double sumsq, int64_t M) { return sqrt(sumsq / (double)M); }
+
+// Starting step, first half: d0, d1 from S(n0); h0.  With a user h0 the
+// first attempt is prepared right away.  Whole workgroup.
+__device__ inline void init_h0_step(const IntegDev &I, int njobs)
+{
+    IntegCtl &c = *I.ctl;
+    if (c.done) return;
+    double tot[SMOL_EPART];
+    block_sum_epart(I.epart, njobs, tot);
+    if (threadIdx.x) return;
+    c.n_rhs = 1;
+    if (tot[5] > 0.0) {
+        c.status = ST_ENONFINITE;
+        c.done = 1;
+        c.n_rhs = 0;
+        return;
+    }
+    const double d0 = rms_of(tot[0], I.M), d1 = rms_of(tot[1], I.M);
+    double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+    if (h0 > c.t_end) h0 = c.t_end;
+    c.h0 = h0;
+    c.err = d1;  // kept for the second half
+    if (c.h0_user > 0.0) {
+        c.h = c.h0_user > c.t_end ? c.t_end : c.h0_user;
+        prepare_attempt(c, true);
+    }
+}
+
+// Starting step, second half (Hairer, Norsett & Wanner I, Sec. II.4).
+// Whole workgroup.
+__device__ inline void init_h_step(const IntegDev &I, int njobs)
+{
+    IntegCtl &c = *I.ctl;
+    if (c.done) return;
+    double tot[SMOL_EPART];
+    block_sum_epart(I.epart, njobs, tot);
+    if (threadIdx.x) return;
+    const Tableau &T = c_tab[c.method];
+    c.n_rhs = 2;
+    const double d1 = c.err, h0 = c.h0;
+    const double d2 = rms_of(tot[0], I.M) / h0;
+    double h1;
+    if (d1 <= 1e-15 && d2 <= 1e-15)
+        h1 = fmax(1e-6, h0 * 1e-3);
+    else
+        h1 = pow(0.01 / fmax(d1, d2), 1.0 / (double)(T.q + 1));
+    double h = 100.0 * h0;
+    if (h1 < h) h = h1;
+    if (c.t_end < h) h = c.t_end;
+    c.h = h;
+    c.err = 0.0;
+    prepare_attempt(c, true);
+}
+
+// Accept / reject and the next step size (PI controller), after the last
+// stage; run by one whole workgroup.
+__device__ inline void controller_step(const IntegDev &I, int njobs)
+{
+    IntegCtl &c = *I.ctl;
+    if (c.done) return;
+    double tot[SMOL_EPART];
+    block_sum_epart(I.epart, njobs, tot);
+    if (threadIdx.x) return;
+    const Tableau &T = c_tab[c.method];
+    const int k = T.q + 1;
+    const double err = rms_of(tot[0], I.M);
+    c.err = err;
+    c.attempts += 1;
+    c.n_rhs += T.S - 1;
+    const bool accept = err <= 1.0;
+    if (c.log && c.attempts <= c.log_cap) {
+        double *row = c.log + (c.attempts - 1) * 9;
+        row[0] = c.t;
+        row[1] = c.h;
+        row[2] = err;
+        row[3] = accept ? 1.0 : 0.0;
+        row[4] = accept ? c.t_new : c.t;
+        row[5] = tot[1];
+        row[6] = tot[2];
+        row[7] = tot[3];
+        row[8] = tot[4];
+    }
+    // a NaN norm or a non-finite new state ends the run (state kept)
+    if (isnan(err) || tot[5] > 0.0) {
+        c.status = ST_ENONFINITE;
+        c.done = 1;
+        return;
+    }
+    if (accept) {
+        double fac;
+        if (err == 0.0)
+            fac = c.facmax;
+        else
+            fac = c.safety * pow(err, -c.alpha) * pow(c.err_prev, c.beta);
+        if (fac > c.facmax) fac = c.facmax;
+        if (fac < c.facmin) fac = c.facmin;
+        if (c.rejected && fac > 1.0) fac = 1.0;
+        c.err_prev = fmax(err, 1e-4);
+        c.t = c.t_new;
+        c.h = c.h * fac;
+        c.cur ^= 1;
+        c.kp ^= 1;
+        c.n_accept += 1;
+        c.rejected = 0;
+        if (c.t >= c.t_end) {
+            c.status = ST_OK;
+            c.done = 1;
+            return;
+        }
+        prepare_attempt(c, true);
+    } else {
+        double fac = c.safety * pow(err, -1.0 / (double)k);
+        if (fac < c.facmin) fac = c.facmin;
+        c.h = c.h * fac;
+        c.rejected = 1;
+        c.n_reject += 1;
+        prepare_attempt(c, false);
+    }
 }

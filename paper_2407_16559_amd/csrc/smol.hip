@@ -9,11 +9,11 @@
 #include <tuple>
 #include <vector>
 
-#include "../../include/smol.h"
-#include "integrate.h"
+#include "host.h"
+
+SMOL_HIDDEN std::mutex g_mu;
 
 #define SMOL_VERSION "0.1.0"
-#define SMOL_GRAPH_ATTEMPTS 4
 
 // --------------------------------------------------------------------------
 // Kernels (multi-launch form of the three phases)
@@ -119,145 +119,9 @@ __global__ __launch_bounds__(SMOL_WG) void k_int_C(IntegDev I, int stage, int nu
     if (unit < nunits) PhaseC<N1, N2, T>::run(P, ep, unit, (T *)lds);
 }
 
-// Deterministic block reduction of epart rows (fixed strided order, then a
-// fixed tree); thread 0 receives the totals.
-__device__ inline void block_sum_epart(const double *ep, int njobs, double *tot)
-{
-    __shared__ double sh[SMOL_WG][SMOL_EPART];
-    const int tid = threadIdx.x;
-    double acc[SMOL_EPART];
-    for (int q = 0; q < SMOL_EPART; ++q) acc[q] = 0.0;
-    for (int j = tid; j < njobs; j += SMOL_WG)
-        for (int q = 0; q < SMOL_EPART; ++q) acc[q] += ep[(int64_t)j * SMOL_EPART + q];
-    for (int q = 0; q < SMOL_EPART; ++q) sh[tid][q] = acc[q];
-    __syncthreads();
-    for (int off = SMOL_WG / 2; off >= 1; off >>= 1) {
-        if (tid < off)
-            for (int q = 0; q < SMOL_EPART; ++q) sh[tid][q] += sh[tid + off][q];
-        __syncthreads();
-    }
-    if (tid == 0)
-        for (int q = 0; q < SMOL_EPART; ++q) tot[q] = sh[0][q];
-}
-
-__device__ __forceinline__ double rms_of(double sumsq, int64_t M) { return sqrt(sumsq / (double)M); }
-
-// Starting step, first half: d0, d1 from S(n0); h0.  With a user h0 the
-// first attempt is prepared right away.
-__global__ __launch_bounds__(SMOL_WG) void k_init_h0(IntegDev I, int njobs)
-{
-    IntegCtl &c = *I.ctl;
-    if (c.done) return;
-    double tot[SMOL_EPART];
-    block_sum_epart(I.epart, njobs, tot);
-    if (threadIdx.x) return;
-    c.n_rhs = 1;
-    if (tot[5] > 0.0) {
-        c.status = ST_ENONFINITE;
-        c.done = 1;
-        c.n_rhs = 0;
-        return;
-    }
-    const double d0 = rms_of(tot[0], I.M), d1 = rms_of(tot[1], I.M);
-    double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
-    if (h0 > c.t_end) h0 = c.t_end;
-    c.h0 = h0;
-    c.err = d1;  // kept for the second half
-    if (c.h0_user > 0.0) {
-        c.h = c.h0_user > c.t_end ? c.t_end : c.h0_user;
-        prepare_attempt(c, true);
-    }
-}
-
-// Starting step, second half (Hairer, Norsett & Wanner I, Sec. II.4).
-__global__ __launch_bounds__(SMOL_WG) void k_init_h(IntegDev I, int njobs)
-{
-    IntegCtl &c = *I.ctl;
-    if (c.done) return;
-    double tot[SMOL_EPART];
-    block_sum_epart(I.epart, njobs, tot);
-    if (threadIdx.x) return;
-    const Tableau &T = c_tab[c.method];
-    c.n_rhs = 2;
-    const double d1 = c.err, h0 = c.h0;
-    const double d2 = rms_of(tot[0], I.M) / h0;
-    double h1;
-    if (d1 <= 1e-15 && d2 <= 1e-15)
-        h1 = fmax(1e-6, h0 * 1e-3);
-    else
-        h1 = pow(0.01 / fmax(d1, d2), 1.0 / (double)(T.q + 1));
-    double h = 100.0 * h0;
-    if (h1 < h) h = h1;
-    if (c.t_end < h) h = c.t_end;
-    c.h = h;
-    c.err = 0.0;
-    prepare_attempt(c, true);
-}
-
-// Accept / reject and the next step size (PI controller), after the last stage.
-__global__ __launch_bounds__(SMOL_WG) void k_ctrl(IntegDev I, int njobs)
-{
-    IntegCtl &c = *I.ctl;
-    if (c.done) return;
-    double tot[SMOL_EPART];
-    block_sum_epart(I.epart, njobs, tot);
-    if (threadIdx.x) return;
-    const Tableau &T = c_tab[c.method];
-    const int k = T.q + 1;
-    const double err = rms_of(tot[0], I.M);
-    c.err = err;
-    c.attempts += 1;
-    c.n_rhs += T.S - 1;
-    const bool accept = err <= 1.0;
-    if (c.log && c.attempts <= c.log_cap) {
-        double *row = c.log + (c.attempts - 1) * 9;
-        row[0] = c.t;
-        row[1] = c.h;
-        row[2] = err;
-        row[3] = accept ? 1.0 : 0.0;
-        row[4] = accept ? c.t_new : c.t;
-        row[5] = tot[1];
-        row[6] = tot[2];
-        row[7] = tot[3];
-        row[8] = tot[4];
-    }
-    // a NaN norm or a non-finite new state ends the run (state kept)
-    if (isnan(err) || tot[5] > 0.0) {
-        c.status = ST_ENONFINITE;
-        c.done = 1;
-        return;
-    }
-    if (accept) {
-        double fac;
-        if (err == 0.0)
-            fac = c.facmax;
-        else
-            fac = c.safety * pow(err, -c.alpha) * pow(c.err_prev, c.beta);
-        if (fac > c.facmax) fac = c.facmax;
-        if (fac < c.facmin) fac = c.facmin;
-        if (c.rejected && fac > 1.0) fac = 1.0;
-        c.err_prev = fmax(err, 1e-4);
-        c.t = c.t_new;
-        c.h = c.h * fac;
-        c.cur ^= 1;
-        c.kp ^= 1;
-        c.n_accept += 1;
-        c.rejected = 0;
-        if (c.t >= c.t_end) {
-            c.status = ST_OK;
-            c.done = 1;
-            return;
-        }
-        prepare_attempt(c, true);
-    } else {
-        double fac = c.safety * pow(err, -1.0 / (double)k);
-        if (fac < c.facmin) fac = c.facmin;
-        c.h = c.h * fac;
-        c.rejected = 1;
-        c.n_reject += 1;
-        prepare_attempt(c, false);
-    }
-}
+__global__ __launch_bounds__(SMOL_WG) void k_init_h0(IntegDev I, int njobs) { init_h0_step(I, njobs); }
+__global__ __launch_bounds__(SMOL_WG) void k_init_h(IntegDev I, int njobs) { init_h_step(I, njobs); }
+__global__ __launch_bounds__(SMOL_WG) void k_ctrl(IntegDev I, int njobs) { controller_step(I, njobs); }
 
 // --------------------------------------------------------------------------
 // Host side
@@ -265,20 +129,7 @@ __global__ __launch_bounds__(SMOL_WG) void k_ctrl(IntegDev I, int njobs)
 
 namespace {
 
-int hip_fail(hipError_t e, const char *what)
-{
-    if (getenv("SMOL_DEBUG")) fprintf(stderr, "libsmol: %s: %s\n", what, hipGetErrorString(e));
-    return SMOL_EDEVICE;
-}
-#define HIP_TRY(x)                                   \
-    do {                                             \
-        hipError_t e_ = (x);                         \
-        if (e_ != hipSuccess) return hip_fail(e_, #x); \
-    } while (0)
 
-struct DevRoots {
-    cd *tw = nullptr, *fine = nullptr;
-};
 
 struct Plan {
     int dev = -1;
@@ -297,18 +148,13 @@ struct Plan {
     hipGraphExec_t graph[2] = {nullptr, nullptr};
 };
 
-std::mutex g_mu;
 std::map<int, DevRoots> g_roots;
 std::map<std::tuple<int, int64_t, int, int>, Plan *> g_plans;
 
-int ilog2_ceil(int64_t x)
-{
-    int l = 0;
-    while ((1LL << l) < x) ++l;
-    return l;
-}
 
-int get_roots(int dev, DevRoots **out)
+}  // namespace
+
+SMOL_HIDDEN int get_roots(int dev, DevRoots **out)
 {
     auto it = g_roots.find(dev);
     if (it != g_roots.end()) {
@@ -331,6 +177,8 @@ int get_roots(int dev, DevRoots **out)
     *out = &g_roots[dev];
     return SMOL_OK;
 }
+
+namespace {
 
 void free_plan(Plan *p)
 {
@@ -430,36 +278,6 @@ int launch_rhs_t(const RhsPlanDev &P, const Pro &in, const Epi &ep, hipStream_t 
     return SMOL_OK;
 }
 
-// Call F::template run<N1, N2, T>(args...) for the transform shape of logL
-// and the complex arithmetic of `precision` (cd: FP64, cff: float-float).
-template <class F, class... Args>
-int with_shape(int logL, int precision, Args &&...args)
-{
-    switch (logL) {
-#define CASE(LL, A, B)                                                        \
-    case LL:                                                                  \
-        return precision == SMOL_FP32X2                                       \
-                   ? F::template run<(1 << A), (1 << B), cff>(args...)        \
-                   : F::template run<(1 << A), (1 << B), cd>(args...);
-        CASE(6, 3, 3)
-        CASE(7, 4, 3)
-        CASE(8, 4, 4)
-        CASE(9, 5, 4)
-        CASE(10, 5, 5)
-        CASE(11, 6, 5)
-        CASE(12, 6, 6)
-        CASE(13, 7, 6)
-        CASE(14, 7, 7)
-        CASE(15, 8, 7)
-        CASE(16, 8, 8)
-        CASE(17, 9, 8)
-        CASE(18, 9, 9)
-        CASE(19, 10, 9)
-        CASE(20, 10, 10)
-#undef CASE
-    default: return SMOL_EUNSUPPORTED;
-    }
-}
 
 struct LaunchRhs {
     template <int N1, int N2, class T>
@@ -564,7 +382,9 @@ int get_step_graph(Plan *p, const IntegDev &I, int method, hipGraphExec_t *out)
     return SMOL_OK;
 }
 
-void stats_from(const IntegCtl &c, smol_stats *st)
+}  // namespace
+
+SMOL_HIDDEN void stats_from(const IntegCtl &c, smol_stats *st)
 {
     if (!st) return;
     st->n_rhs = c.n_rhs;
@@ -577,7 +397,7 @@ void stats_from(const IntegCtl &c, smol_stats *st)
     st->n_fallback = c.n_fallback;
 }
 
-int check_common(int64_t M, int32_t R, const double *U, const double *V, double lambda)
+SMOL_HIDDEN int check_common(int64_t M, int32_t R, const double *U, const double *V, double lambda)
 {
     if (M < 1 || R < 1 || R > SMOL_MAX_R || !U || !V) return SMOL_EINVAL;
     if (!std::isfinite(lambda) || lambda < 0) return SMOL_EINVAL;
@@ -585,7 +405,6 @@ int check_common(int64_t M, int32_t R, const double *U, const double *V, double 
     return SMOL_OK;
 }
 
-}  // namespace
 
 // --------------------------------------------------------------------------
 // C ABI
@@ -831,11 +650,6 @@ extern "C" int smol_profile_rhs(int64_t M, int32_t R, const double *U, const dou
 }
 
 // ---- entry points not built yet ------------------------------------------
-extern "C" int smol_integrate_batch(int32_t, const smol_instance *, int32_t, int32_t,
-                                    const smol_options *, smol_stats *, void *)
-{
-    return SMOL_EUNSUPPORTED;
-}
 extern "C" int smol_proposer_set(const float *, int32_t, void *) { return SMOL_EUNSUPPORTED; }
 extern "C" int smol_proposer_train(const float *, const float *, int64_t, float *, int32_t,
                                    int32_t, float, float, uint64_t, float *, void *)
