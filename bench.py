@@ -56,6 +56,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--t-end", type=float, default=None, help="shorter runs (profiling)")
+    ap.add_argument("--workload", choices=["single", "batch"], default="single",
+                    help="single: the M=65536 DP5 instance (default); batch: the 256-instance sweep")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -69,6 +71,8 @@ def main():
     import workloads as W
 
     dev = torch.device("cuda:0")
+    if args.workload == "batch":
+        return bench_batch(args, smol, W, torch, dev)
     c = W.CONFIGS[2]
     t_end = args.t_end if args.t_end else c["t_end"]
     U, V, lam, n0 = W.config_instance(2)
@@ -134,6 +138,58 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(U, V, lam, n0, 6)
+    print(json.dumps(line), flush=True)
+
+
+def bench_batch(args, smol, W, torch, dev):
+    """Batched sweep: 256 seeded instances (M log-uniform in [2^12, 2^17],
+    a in [0.05, 0.5], lam log-uniform in [1e-3, 1e-1], exponential starts),
+    BS3, rtol 1e-6, atol 1e-12, t_end 1e3, in one batched run per bench step;
+    compared with one-by-one single-instance runs of every 16th instance,
+    extrapolated to all 256."""
+    c = W.CONFIGS[3]
+    t_end = args.t_end if args.t_end else c["t_end"]
+    draws = W.batch_draws(c["n_inst"], seed=c["seed"])
+    insts = []
+    for d in draws:
+        U, V, lam, n0 = W.batch_instance(d)
+        insts.append(dict(U=torch.from_numpy(U).to(dev), V=torch.from_numpy(V).to(dev), lam=lam,
+                          n0=torch.from_numpy(n0).to(dev), t_end=t_end, rtol=c["rtol"],
+                          atol=c["atol"]))
+    for _ in range(args.warmup):
+        smol.integrate_batch(insts, method="bs3")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        outs, stats = smol.integrate_batch(insts, method="bs3")
+    torch.cuda.synchronize()
+    elapsed = (time.perf_counter() - t0) / args.steps
+    n_acc = sum(s["n_accept"] for s in stats)
+    t0 = time.perf_counter()
+    sample = list(range(0, len(insts), 16))
+    for i in sample:
+        d = insts[i]
+        smol.integrate(d["U"], d["V"], d["lam"], d["n0"], t_end, d["rtol"], d["atol"],
+                       method="bs3", raise_on_error=True)
+    torch.cuda.synchronize()
+    single = (time.perf_counter() - t0) * len(insts) / len(sample)
+    line = {
+        "metric": "accepted RK steps/s over all instances (batched sweep)",
+        "value": n_acc / elapsed,
+        "unit": "accepted steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"batched-sweep: 256 instances, M log-uniform 2^12..2^17, BS3(2) PI, "
+                               f"rtol=1e-6, atol=1e-12, t_end={t_end:g}", "parallelism": "1 GPU"},
+        "batch_time_s": elapsed,
+        "single_instance_runs_extrapolated_s": single,
+        "speedup_vs_single_runs": single / elapsed,
+        "accepted_steps_total": n_acc,
+        "max_accepted_steps_one_instance": max(s["n_accept"] for s in stats),
+        "all_ok": all(s["status"] == 0 for s in stats),
+    }
     print(json.dumps(line), flush=True)
 
 

@@ -20,6 +20,7 @@ struct BatchDev {
     const int *owner[3];    // instance of each block per kernel
     const int *nC;          // finish units per instance
     const int *redA;        // column-pass reduction jobs per instance
+    const int *active;      // instances still running (one controller workgroup each)
 };
 
 #define SMOL_SHAPES(X) \
@@ -68,7 +69,7 @@ __global__ __launch_bounds__(SMOL_WG) void kb_B(BatchDev B, int stage)
     }
 }
 
-template <class T>
+template <class T, bool FUSE>
 __global__ __launch_bounds__(SMOL_WG) void kb_C(BatchDev B, int stage)
 {
     extern __shared__ cd lds[];
@@ -81,53 +82,99 @@ __global__ __launch_bounds__(SMOL_WG) void kb_C(BatchDev B, int stage)
     const int unit = blockIdx.x - B.first[2][b];
     switch (B.logL[b]) {
 #define X(LL, A, Bb) \
-    case LL: PhaseC<(1 << A), (1 << Bb), T>::run(P, ep, unit, (T *)lds); break;
+    case LL: PhaseC<(1 << A), (1 << Bb), T>::template run<FUSE>(P, ep, unit, (T *)lds); break;
         SMOL_SHAPES(X)
 #undef X
     }
 }
 
-// one workgroup per instance
+// one workgroup per listed instance
 __global__ __launch_bounds__(SMOL_WG) void kb_init_h0(BatchDev B)
 {
-    init_h0_step(B.inst[blockIdx.x], B.nC[blockIdx.x]);
+    const int b = B.active[blockIdx.x];
+    init_h0_step(B.inst[b], B.nC[b]);
 }
 __global__ __launch_bounds__(SMOL_WG) void kb_init_h(BatchDev B)
 {
-    init_h_step(B.inst[blockIdx.x], B.nC[blockIdx.x]);
+    const int b = B.active[blockIdx.x];
+    init_h_step(B.inst[b], B.nC[b]);
 }
 __global__ __launch_bounds__(SMOL_WG) void kb_ctrl(BatchDev B)
 {
-    controller_step(B.inst[blockIdx.x], B.nC[blockIdx.x]);
+    const int b = B.active[blockIdx.x];
+    controller_step(B.inst[b], B.nC[b]);
 }
 
 namespace {
 
 struct BatchRun {
-    int n = 0, R_max = 0;
-    std::vector<int> logL, units[3], red, ldsmax;
+    int n = 0;
+    std::vector<int> logL, units[3], ldsn[4];  // ldsn[3]: fused finish
     std::vector<size_t> off;     // arena offset of each instance
-    size_t arena_bytes = 0;
-    int total[3] = {0, 0, 0};
-    size_t lds[3] = {0, 0, 0};
+    int total[3] = {0, 0, 0};    // blocks of each kernel over the listed instances
+    int nact = 0;                // listed instances
+    size_t lds[4] = {0, 0, 0, 0};
 };
+
+// Block-to-instance tables over the instances in `ids` (device buffers
+// sized for all instances are reused).
+int build_tables(BatchRun &br, const std::vector<int> &ids, int *dfirst[3], int *downer[3],
+                 int *dactive, hipStream_t s)
+{
+    std::vector<int> first[3], owner[3];
+    for (int k = 0; k < 3; ++k) {
+        first[k].assign(br.n + 1, 0);
+        br.total[k] = 0;
+        br.lds[k] = 0;
+    }
+    br.lds[3] = 0;
+    for (int i : ids) {
+        const size_t lf = sizeof(cd) * (size_t)br.ldsn[3][i];
+        if (lf > br.lds[3]) br.lds[3] = lf;
+        for (int k = 0; k < 3; ++k) {
+            first[k][i] = br.total[k];
+            for (int j = 0; j < br.units[k][i]; ++j) owner[k].push_back(i);
+            br.total[k] += br.units[k][i];
+            const size_t lb = sizeof(cd) * (size_t)br.ldsn[k][i];
+            if (lb > br.lds[k]) br.lds[k] = lb;
+        }
+    }
+    br.nact = (int)ids.size();
+    for (int k = 0; k < 3; ++k) {
+        HIP_TRY(hipMemcpyAsync(dfirst[k], first[k].data(), sizeof(int) * (br.n + 1),
+                               hipMemcpyHostToDevice, s));
+        if (br.total[k])
+            HIP_TRY(hipMemcpyAsync(downer[k], owner[k].data(), sizeof(int) * br.total[k],
+                                   hipMemcpyHostToDevice, s));
+    }
+    HIP_TRY(hipMemcpyAsync(dactive, ids.data(), sizeof(int) * ids.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));  // host vectors die here
+    return SMOL_OK;
+}
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Same kernel sequence as a single instance: A only up to stage 2, the
+// finish of stages 2..S-1 fused with the next column pass.
 template <class T>
-void launch_stage(const BatchDev &B, const BatchRun &br, int stage, hipStream_t s)
+void launch_stage(const BatchDev &B, const BatchRun &br, int stage, int S, hipStream_t s)
 {
-    hipLaunchKernelGGL(kb_A<T>, dim3(br.total[0]), dim3(SMOL_WG), br.lds[0], s, B, stage);
+    if (stage <= 2)
+        hipLaunchKernelGGL(kb_A<T>, dim3(br.total[0]), dim3(SMOL_WG), br.lds[0], s, B, stage);
     hipLaunchKernelGGL(kb_B<T>, dim3(br.total[1]), dim3(SMOL_WG), br.lds[1], s, B, stage);
-    hipLaunchKernelGGL(kb_C<T>, dim3(br.total[2]), dim3(SMOL_WG), br.lds[2], s, B, stage);
+    if (stage >= 2 && stage < S)
+        hipLaunchKernelGGL((kb_C<T, true>), dim3(br.total[2]), dim3(SMOL_WG), br.lds[3], s, B, stage);
+    else
+        hipLaunchKernelGGL((kb_C<T, false>), dim3(br.total[2]), dim3(SMOL_WG), br.lds[2], s, B, stage);
 }
 
-void launch_stage_p(int precision, const BatchDev &B, const BatchRun &br, int stage, hipStream_t s)
+void launch_stage_p(int precision, const BatchDev &B, const BatchRun &br, int stage, int S,
+                    hipStream_t s)
 {
     if (precision == SMOL_FP32X2)
-        launch_stage<cff>(B, br, stage, s);
+        launch_stage<cff>(B, br, stage, S, s);
     else
-        launch_stage<cd>(B, br, stage, s);
+        launch_stage<cd>(B, br, stage, S, s);
 }
 
 }  // namespace
@@ -161,16 +208,16 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
     int rc = get_roots(dev, &roots);
     if (rc) return rc;
 
-    // ---- sizes, block tables and arena layout
+    // ---- sizes and arena layout
     BatchRun br;
     br.n = n_inst;
-    std::vector<int> first[3], owner[3], nC(n_inst), redA(n_inst);
-    for (int k = 0; k < 3; ++k) first[k].resize(n_inst + 1);
+    std::vector<int> nC(n_inst), redA(n_inst);
     br.logL.resize(n_inst);
     br.off.resize(n_inst);
-    size_t at = 0;
-    const size_t ctl_bytes = align256(sizeof(IntegCtl) * n_inst);
-    at = ctl_bytes;
+    for (int k = 0; k < 3; ++k) br.units[k].resize(n_inst);
+    for (int k = 0; k < 4; ++k) br.ldsn[k].resize(n_inst);
+    size_t at = align256(sizeof(IntegCtl) * n_inst);
+    int64_t blocks[3] = {0, 0, 0};
     for (int i = 0; i < n_inst; ++i) {
         const smol_instance &q = inst[i];
         const int logL = fft_log2(q.M);
@@ -178,12 +225,11 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
         int u[8];
         if ((rc = with_shape<ShapeUnits>(logL, precision, (int)q.R, u))) return rc;
         for (int k = 0; k < 3; ++k) {
-            first[k][i] = br.total[k];
-            for (int j = 0; j < u[k]; ++j) owner[k].push_back(i);
-            br.total[k] += u[k];
-            const size_t lb = sizeof(cd) * (size_t)u[4 + k];
-            if (lb > br.lds[k]) br.lds[k] = lb;
+            br.units[k][i] = u[k];
+            br.ldsn[k][i] = u[4 + k];
+            blocks[k] += u[k];
         }
+        br.ldsn[3][i] = u[7];
         nC[i] = u[2];
         redA[i] = u[3];
         const int64_t L = 1LL << logL, half = L / 2, N2 = 1LL << (logL / 2);
@@ -194,17 +240,18 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
         at += align256(sizeof(cd) * (size_t)(q.R * L + L / 2));           // spectra
         at += align256(sizeof(double) * (size_t)(N2 * q.R * 4 + 4 * q.R + N2 * SMOL_EPART));
     }
-    for (int k = 0; k < 3; ++k) first[k][n_inst] = br.total[k];
+    for (int k = 0; k < 3; ++k)
+        if (blocks[k] > (1LL << 30)) return SMOL_EUNSUPPORTED;
     const size_t tab_off = at;
     size_t tab_bytes = 0;
     tab_bytes += align256(sizeof(IntegDev) * n_inst);
-    tab_bytes += align256(sizeof(int) * n_inst) * 3;  // logL, nC, redA
+    tab_bytes += align256(sizeof(int) * n_inst) * 4;  // logL, nC, redA, active list
     for (int k = 0; k < 3; ++k)
-        tab_bytes += align256(sizeof(int) * (n_inst + 1)) + align256(sizeof(int) * br.total[k]);
-    br.arena_bytes = at + tab_bytes;
+        tab_bytes += align256(sizeof(int) * (n_inst + 1)) + align256(sizeof(int) * blocks[k]);
+    const size_t arena_bytes = at + tab_bytes;
 
     char *arena = nullptr;
-    if (hipMalloc(&arena, br.arena_bytes) != hipSuccess) return SMOL_ENOMEM;
+    if (hipMalloc(&arena, arena_bytes) != hipSuccess) return SMOL_ENOMEM;
     IntegCtl *hctl = nullptr;
     hipStream_t cap = nullptr;
     hipGraphExec_t ge = nullptr;
@@ -274,20 +321,41 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
         }
         // ---- tables
         char *tp = arena + tab_off;
-        auto put = [&](const void *src, size_t bytes) -> char * {
+        auto take = [&](size_t bytes) -> char * {
             char *d = tp;
             tp += align256(bytes);
-            return (hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, s) == hipSuccess) ? d : nullptr;
+            return d;
         };
         BatchDev B;
-        B.inst = (const IntegDev *)put(hdev.data(), sizeof(IntegDev) * n_inst);
-        B.logL = (const int *)put(br.logL.data(), sizeof(int) * n_inst);
-        B.nC = (const int *)put(nC.data(), sizeof(int) * n_inst);
-        B.redA = (const int *)put(redA.data(), sizeof(int) * n_inst);
+        IntegDev *dinst = (IntegDev *)take(sizeof(IntegDev) * n_inst);
+        int *dlogL = (int *)take(sizeof(int) * n_inst);
+        int *dnC = (int *)take(sizeof(int) * n_inst);
+        int *dredA = (int *)take(sizeof(int) * n_inst);
+        int *dactive = (int *)take(sizeof(int) * n_inst);
+        int *dfirst[3], *downer[3];
         for (int k = 0; k < 3; ++k) {
-            B.first[k] = (const int *)put(first[k].data(), sizeof(int) * (n_inst + 1));
-            B.owner[k] = (const int *)put(owner[k].data(), sizeof(int) * br.total[k]);
+            dfirst[k] = (int *)take(sizeof(int) * (n_inst + 1));
+            downer[k] = (int *)take(sizeof(int) * blocks[k]);
         }
+        if (hipMemcpyAsync(dinst, hdev.data(), sizeof(IntegDev) * n_inst, hipMemcpyHostToDevice, s) ||
+            hipMemcpyAsync(dlogL, br.logL.data(), sizeof(int) * n_inst, hipMemcpyHostToDevice, s) ||
+            hipMemcpyAsync(dnC, nC.data(), sizeof(int) * n_inst, hipMemcpyHostToDevice, s) ||
+            hipMemcpyAsync(dredA, redA.data(), sizeof(int) * n_inst, hipMemcpyHostToDevice, s)) {
+            rc = SMOL_EDEVICE;
+            break;
+        }
+        B.inst = dinst;
+        B.logL = dlogL;
+        B.nC = dnC;
+        B.redA = dredA;
+        B.active = dactive;
+        for (int k = 0; k < 3; ++k) {
+            B.first[k] = dfirst[k];
+            B.owner[k] = downer[k];
+        }
+        std::vector<int> ids;
+        for (int i = 0; i < n_inst; ++i)
+            if (!hctl[i].done) ids.push_back(i);
         if (hipMemcpyAsync(dctl, hctl, sizeof(IntegCtl) * n_inst, hipMemcpyHostToDevice, s) != hipSuccess) {
             rc = SMOL_EDEVICE;
             break;
@@ -301,44 +369,53 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
             hipLaunchKernelGGL(k_to_tr, dim3(128), dim3(256), 0, s, q.n0, I.nb[0], q.M, 1, q.M, I.Mt, I.logL);
         }
         // ---- starting step for every instance
-        launch_stage_p(precision, B, br, 0, s);
-        hipLaunchKernelGGL(kb_init_h0, dim3(n_inst), dim3(SMOL_WG), 0, s, B);
-        if (!(o.h0 > 0)) {
-            launch_stage_p(precision, B, br, 1, s);
-            hipLaunchKernelGGL(kb_init_h, dim3(n_inst), dim3(SMOL_WG), 0, s, B);
+        if (ids.empty()) {
+            for (int i = 0; i < n_inst; ++i) stats_from(hctl[i], &stats[i]);
+        }
+        if (!ids.empty() && (rc = build_tables(br, ids, dfirst, downer, dactive, s))) break;
+        if (!ids.empty()) {
+            launch_stage_p(precision, B, br, 0, 0, s);
+            hipLaunchKernelGGL(kb_init_h0, dim3(br.nact), dim3(SMOL_WG), 0, s, B);
+            if (!(o.h0 > 0)) {
+                launch_stage_p(precision, B, br, 1, 0, s);
+                hipLaunchKernelGGL(kb_init_h, dim3(br.nact), dim3(SMOL_WG), 0, s, B);
+            }
         }
         if (hipGetLastError() != hipSuccess) {
             rc = SMOL_EDEVICE;
             break;
         }
-        // ---- graph of SMOL_GRAPH_ATTEMPTS attempts for all instances
+        // ---- graph of SMOL_GRAPH_ATTEMPTS attempts over the listed instances
         if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
             rc = SMOL_EDEVICE;
             break;
         }
         const int S = method == SMOL_DP54 ? 7 : 4;
-        hipGraph_t g;
-        if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-            rc = SMOL_EDEVICE;
-            break;
-        }
-        for (int a = 0; a < SMOL_GRAPH_ATTEMPTS; ++a) {
-            for (int st = 2; st <= S; ++st) launch_stage_p(precision, B, br, st, cap);
-            hipLaunchKernelGGL(kb_ctrl, dim3(n_inst), dim3(SMOL_WG), 0, cap, B);
-        }
-        if (hipStreamEndCapture(cap, &g) != hipSuccess) {
-            rc = SMOL_EDEVICE;
-            break;
-        }
-        hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) {
-            rc = SMOL_EDEVICE;
-            break;
-        }
-        // ---- replay until every instance is done
+        auto capture = [&]() -> int {
+            if (ge) (void)hipGraphExecDestroy(ge);
+            ge = nullptr;
+            hipGraph_t g;
+            HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+            for (int a = 0; a < SMOL_GRAPH_ATTEMPTS; ++a) {
+                for (int st = 2; st <= S; ++st) launch_stage_p(precision, B, br, st, S, cap);
+                hipLaunchKernelGGL(kb_ctrl, dim3(br.nact), dim3(SMOL_WG), 0, cap, B);
+            }
+            HIP_TRY(hipStreamEndCapture(cap, &g));
+            hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HIP_TRY(e);
+            return SMOL_OK;
+        };
+        // ---- replay until every instance is done; when the running set
+        // halves, rebuild the tables over it and capture again, so finished
+        // instances stop costing workgroups
         int64_t chunk = 1;
-        for (;;) {
+        bool need_capture = !ids.empty();
+        while (!ids.empty()) {
+            if (need_capture) {
+                if ((rc = capture())) break;
+                need_capture = false;
+            }
             for (int64_t k = 0; k < chunk && rc == SMOL_OK; ++k)
                 if (hipGraphLaunch(ge, s) != hipSuccess) rc = SMOL_EDEVICE;
             if (rc) break;
@@ -347,20 +424,30 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
                 rc = SMOL_EDEVICE;
                 break;
             }
+            std::vector<int> live;
             double most = 0.0;
-            bool all = true;
-            for (int i = 0; i < n_inst; ++i) {
+            for (int i : ids) {
                 if (hctl[i].done) continue;
-                all = false;
+                live.push_back(i);
                 double est = hctl[i].h > 0 ? (hctl[i].t_end - hctl[i].t) / hctl[i].h : 1e9;
                 if (!(est < 1e9)) est = 1e9;
                 if (est > most) most = est;
             }
-            if (all) break;
-            chunk = (int64_t)(0.8 * most / SMOL_GRAPH_ATTEMPTS) + 1;
-            if (chunk > 64) chunk = 64;
+            if (live.empty()) break;
+            if (2 * live.size() <= ids.size()) {
+                ids = live;
+                if ((rc = build_tables(br, ids, dfirst, downer, dactive, s))) break;
+                need_capture = true;
+            }
+            chunk = (int64_t)(0.5 * most / SMOL_GRAPH_ATTEMPTS) + 1;
+            if (chunk > 16) chunk = 16;
         }
         if (rc) break;
+        if (hipMemcpyAsync(hctl, dctl, sizeof(IntegCtl) * n_inst, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            rc = SMOL_EDEVICE;
+            break;
+        }
         // ---- outputs
         for (int i = 0; i < n_inst; ++i) {
             const IntegDev &I = hdev[i];

@@ -95,6 +95,7 @@ struct ShapeUnits {
         out[4] = PhaseA<N1, N2, T>::LDS;  // dynamic LDS entries of each kernel
         out[5] = PhaseB<N1, N2, T>::LDS;
         out[6] = PhaseC<N1, N2, T>::LDS;
+        out[7] = PhaseC<N1, N2, T>::LDS_FUSE;
         return SMOL_OK;
     }
 };

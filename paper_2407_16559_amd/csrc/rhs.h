@@ -350,12 +350,21 @@ struct PhaseC {
     static constexpr int NPOS = COLS * N1;                     // outputs per unit
     static constexpr int PP = (NPOS + SMOL_WG - 1) / SMOL_WG;  // per thread
     static constexpr int LDS = 64 * F::E;                      // wave 0 scratch
+    // fused with the next column pass: four waves of scratch + the next
+    // stage state of the unit's 2 COLS columns (doubles)
+    // (2 COLS columns x N1/2 rows of doubles = COLS N1 / 2 sixteen-byte entries)
+    static constexpr int LDS_FUSE = SMOL_WAVES * 64 * F::E + COLS * N1 / 2;
     static __host__ __device__ int units() { return HALF / COLS; }
     static __host__ __device__ int jobs() { return units(); }
 
     static constexpr int KMAX = 6;  // stage vectors an epilogue combines
     static constexpr int RPRE = 4;  // ranks whose U, V are prefetched
 
+    // FUSE (stage epilogue only): the unit's outputs y_{i+1} fill exactly the
+    // 2 COLS columns ac+1 and ac+1+N2/2 of the next column pass (the last
+    // unit also owns column 0: it computes size 1 and wraps onto row b+1),
+    // so the workgroup runs that pass itself and writes the next spectra.
+    template <bool FUSE = false>
     __device__ static void run(const RhsPlanDev &P, const Epi &ep, int unit, C *lds)
     {
         __shared__ double sh[SMOL_WAVES * 16];
@@ -443,7 +452,7 @@ struct PhaseC {
             }
         }
         // ---- size 1 (index 0): monomer balance with the shattering gains
-        const bool mono = unit == 0 && tid == 0;
+        const bool mono = unit == units() - 1 && tid == 0;
         double yn1 = 0.0;
         if (mono) {
             const double y1 = ep.y[0];
@@ -462,6 +471,21 @@ struct PhaseC {
 #pragma unroll
             for (int k = 0; k < KMAX; ++k) k1v[k] = (k < nk && ep.coef[k] != 0.0) ? ep.ks[k][0] : 0.0;
             yn1 = finish(ep, 0, 1.0, S1, y1, need_n ? ep.n[0] : 0.0, k1v, nk, acc);
+        }
+        double *ycol = (double *)(lds + SMOL_WAVES * 64 * F::E);
+        if constexpr (FUSE) {
+            // next stage state by (local column, row) for the column pass below
+#pragma unroll
+            for (int j = 0; j < PP; ++j) {
+                if (qv[j] >= 0) {
+                    const int e = tid + j * SMOL_WG;
+                    const int b = e % (N1 / 2), hh = (e / (N1 / 2)) & 1, f = e / N1;
+                    const int wrap = (unit * COLS + f + 1 + hh * HALF) == N2;
+                    const int n1 = b + wrap;
+                    if (n1 < N1 / 2) ycol[(hh * COLS + f) * (N1 / 2) + n1] = yn[j];
+                }
+            }
+            if (mono) ycol[(2 * COLS - 1) * (N1 / 2)] = yn1;
         }
         if (mode == C_STAGE) {
             // reductions of the next stage state, four ranks per pass
@@ -517,6 +541,52 @@ struct PhaseC {
             __syncthreads();
             if (tid < SMOL_EPART)
                 ep.epart[(int64_t)unit * SMOL_EPART + tid] = sum_waves(sh, SMOL_EPART, tid);
+        }
+        if constexpr (FUSE) {
+            __syncthreads();
+            column_pass(P, unit, lds, ycol);
+        }
+    }
+
+    // The next stage's column pass over this unit's 2 COLS columns x R ranks
+    // (same arithmetic as phase A given y), one transform per wave slot.
+    __device__ static void column_pass(const RhsPlanDev &P, int unit, C *lds, const double *ycol)
+    {
+        const int lane = lane_id(), w = wave_id();
+        const int f = lane / F::G, g = lane % F::G;
+        const int64_t M = P.M;
+        FftTw<N1, false, C> tw;
+        tw.load(g, P.rt);
+        const int nj = 2 * COLS * P.R;
+        for (int r0 = 0; r0 < nj; r0 += SMOL_WAVES * F::B) {
+            const int job = r0 + w * F::B + f;
+            if (job < nj) {
+                const int jj = job % (2 * COLS), al = job / (2 * COLS);
+                const int hh = jj / COLS, fc = jj % COLS;
+                const int n2 = (unit * COLS + fc + 1 + hh * HALF) & (N2 - 1);
+                const double *Ua = P.U + (int64_t)al * P.ustride, *Va = P.V + (int64_t)al * P.ustride;
+                C t4[F::E];
+                step_twiddles<F::E, false>(P.rt, P.logL, (uint32_t)n2, g, F::G, t4);
+                C v[F::E];
+#pragma unroll
+                for (int i = 0; i < F::E; ++i) {
+                    v[i] = czero<C>();
+                    if (i < F::E / 2) {
+                        const int n1 = g + i * F::G;
+                        const int64_t idx = (int64_t)n1 * N2 + n2;
+                        if (idx < M - 1) {
+                            const double yv = ycol[jj * (N1 / 2) + n1];
+                            const int64_t q = pos_of(P, idx);
+                            v[i] = from_cd<C>(cd{Ua[q] * yv, Va[q] * yv});
+                        }
+                    }
+                }
+                wave_fft<N1, false>(v, lds + w * 64 * F::E + f * N1, g, tw);
+                C *Za = (C *)P.Z + ((int64_t)al << P.logL) + n2;
+#pragma unroll
+                for (int i = 0; i < F::E; ++i)
+                    Za[(int64_t)(g + i * F::G) * N2] = cmul(v[i], t4[i]);
+            }
         }
     }
 

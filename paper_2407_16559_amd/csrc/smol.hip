@@ -52,7 +52,7 @@ __global__ __launch_bounds__(SMOL_WG) void k_phaseC(RhsPlanDev P, Epi ep, int nu
 {
     extern __shared__ cd lds[];
     const int unit = xcd_remap(blockIdx.x, gridDim.x);
-    if (unit < nunits) PhaseC<N1, N2, T>::run(P, ep, unit, (T *)lds);
+    if (unit < nunits) PhaseC<N1, N2, T>::template run<false>(P, ep, unit, (T *)lds);
 }
 
 // Layout conversion of `rows` vectors of M sizes: natural <-> transposed.
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(SMOL_WG) void k_int_B(IntegDev I, int stage)
     PhaseB<N1, N2, T>::run(P, u, (T *)lds);
 }
 
-template <int N1, int N2, class T>
+template <int N1, int N2, class T, bool FUSE>
 __global__ __launch_bounds__(SMOL_WG) void k_int_C(IntegDev I, int stage, int nunits)
 {
     const IntegCtl &c = *I.ctl;
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(SMOL_WG) void k_int_C(IntegDev I, int stage, int nu
     const RhsPlanDev P = plan_of(I, c);
     const Epi ep = stage_epi(I, c, tab, stage);
     const int unit = xcd_remap(blockIdx.x, gridDim.x);
-    if (unit < nunits) PhaseC<N1, N2, T>::run(P, ep, unit, (T *)lds);
+    if (unit < nunits) PhaseC<N1, N2, T>::template run<FUSE>(P, ep, unit, (T *)lds);
 }
 
 __global__ __launch_bounds__(SMOL_WG) void k_init_h0(IntegDev I, int njobs) { init_h0_step(I, njobs); }
@@ -287,21 +287,29 @@ struct LaunchRhs {
     }
 };
 
-// One stage (or starting-step evaluation) of the integrator: A, B, C.
+// One stage (or starting-step evaluation) of the integrator.  Stages 0..2
+// run A, B, C; from stage 3 on the column pass was done by the previous
+// stage's fused finish, so only B and C run; the finish of stages
+// 2..S-1 is fused with the next column pass.
 struct LaunchStage {
     template <int N1, int N2, class T>
-    static int run(const IntegDev &I, int stage, hipStream_t s)
+    static int run(const IntegDev &I, int stage, int S, hipStream_t s)
     {
         using A = PhaseA<N1, N2, T>;
         using B = PhaseB<N1, N2, T>;
         using C = PhaseC<N1, N2, T>;
         const int nA = A::units(I.R), nC = C::units();
-        hipLaunchKernelGGL((k_int_A<N1, N2, T>), dim3(nA), dim3(SMOL_WG), sizeof(cd) * A::LDS, s, I,
-                           stage, nA);
+        if (stage <= 2)
+            hipLaunchKernelGGL((k_int_A<N1, N2, T>), dim3(nA), dim3(SMOL_WG), sizeof(cd) * A::LDS, s,
+                               I, stage, nA);
         hipLaunchKernelGGL((k_int_B<N1, N2, T>), dim3(B::units() + 1), dim3(SMOL_WG),
                            sizeof(cd) * B::LDS, s, I, stage);
-        hipLaunchKernelGGL((k_int_C<N1, N2, T>), dim3(nC), dim3(SMOL_WG), sizeof(cd) * C::LDS, s, I,
-                           stage, nC);
+        if (stage >= 2 && stage < S)
+            hipLaunchKernelGGL((k_int_C<N1, N2, T, true>), dim3(nC), dim3(SMOL_WG),
+                               sizeof(cd) * C::LDS_FUSE, s, I, stage, nC);
+        else
+            hipLaunchKernelGGL((k_int_C<N1, N2, T, false>), dim3(nC), dim3(SMOL_WG),
+                               sizeof(cd) * C::LDS, s, I, stage, nC);
         HIP_TRY(hipGetLastError());
         return SMOL_OK;
     }
@@ -369,7 +377,7 @@ int get_step_graph(Plan *p, const IntegDev &I, int method, hipGraphExec_t *out)
     const int nC = with_shape<PhaseCJobs>(p->logL, SMOL_FP64);
     for (int a = 0; a < SMOL_GRAPH_ATTEMPTS; ++a) {
         for (int st = 2; st <= S && rc == SMOL_OK; ++st)
-            rc = with_shape<LaunchStage>(p->logL, p->precision, I, st, p->cap);
+            rc = with_shape<LaunchStage>(p->logL, p->precision, I, st, S, p->cap);
         hipLaunchKernelGGL(k_ctrl, dim3(1), dim3(SMOL_WG), 0, p->cap, I, nC);
     }
     hipError_t e = hipStreamEndCapture(p->cap, &g);
@@ -533,10 +541,10 @@ extern "C" int smol_integrate_ex(int64_t M, int32_t R, const double *U, const do
     hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, n0, I.nb[0], M, 1, M, I.Mt, p->logL);
     const int nC = with_shape<PhaseCJobs>(p->logL, SMOL_FP64);
     // starting step: S(n0), h0, S(n0 + h0 f0), h
-    if ((rc = with_shape<LaunchStage>(p->logL, p->precision, I, 0, s))) return rc;
+    if ((rc = with_shape<LaunchStage>(p->logL, p->precision, I, 0, 0, s))) return rc;
     hipLaunchKernelGGL(k_init_h0, dim3(1), dim3(SMOL_WG), 0, s, I, nC);
     if (!(o.h0 > 0)) {
-        if ((rc = with_shape<LaunchStage>(p->logL, p->precision, I, 1, s))) return rc;
+        if ((rc = with_shape<LaunchStage>(p->logL, p->precision, I, 1, 0, s))) return rc;
         hipLaunchKernelGGL(k_init_h, dim3(1), dim3(SMOL_WG), 0, s, I, nC);
     }
     HIP_TRY(hipGetLastError());
