@@ -134,7 +134,8 @@ int smol_integrate_ex(int64_t M, int32_t R, const double *U, const double *V,
                       int32_t precision, const smol_options *opts,
                       double *n_out, smol_stats *stats, void *stream);
 
-/* One instance of a batched run.  All pointers are device pointers. */
+/* One instance of a batched run.  All pointers are device pointers; log
+ * (optional) receives the instance's per-attempt rows as in smol_options. */
 typedef struct {
     int64_t M;
     int32_t R;
@@ -144,6 +145,8 @@ typedef struct {
     const double *n0;
     double *n_out;
     double t_end, rtol, atol;
+    double *log;
+    int64_t log_cap;
 } smol_instance;
 
 /*
@@ -153,28 +156,63 @@ typedef struct {
  * arrays of n_inst entries.  A failing instance records its status in its
  * own stats entry and does not stop the others; the call returns SMOL_OK
  * when every instance is launched and finishes (check each stats[i].status).
+ * Options apply to every instance (opts->log must be NULL: logs are per
+ * instance).  Each phase of a step attempt is one launch over all running
+ * instances (a block-to-instance table), replayed as a hipGraph; the
+ * tables shrink as instances finish.  Every instance reproduces its
+ * single-instance smol_integrate_ex result bitwise.
  */
 int smol_integrate_batch(int32_t n_inst, const smol_instance *inst,
                          int32_t method, int32_t precision,
                          const smol_options *opts, smol_stats *stats,
                          void *stream);
 
-/* Learned step proposer: a 9-64-64-1 tanh MLP in FP32 (4929 parameters,
- * layout W1[64][9], b1[64], W2[64][64], b2[64], W3[64], b3).  Features:
- * log M0..log M3 of the state, log h, log err of the last four attempts.
- * Output: log(h_next / h), clamped to [log 0.2, log 10].  `params` is a
- * device pointer; the library keeps its own copy per device. */
+/* Learned step proposer (the controller option SMOL_CTRL_LEARNED): a
+ * 9-64-64-1 tanh MLP in FP32 (4865 parameters, layout W1[64][9], b1[64],
+ * W2[64][64], b2[64], W3[64], b3).  Features at the decision after an
+ * accepted attempt: log M0..log M3 of the new state divided by 40, log h
+ * divided by 10, log err of the last four attempts (most recent first,
+ * missing ones 0) divided by 10.  Output: log(h_next / h), clamped to
+ * [log 0.2, log 10]; right after a rejection, or for non-finite features,
+ * the PI rule is used instead (counted in smol_stats.n_fallback).  The
+ * embedded error estimate still accepts or rejects every step. */
+
+/* Install the weights used by learned-mode runs on the current device
+ * (device pointer, copied; n_params must be 4865).  Synchronous. */
 int smol_proposer_set(const float *params, int32_t n_params, void *stream);
 
-/* Train the proposer on logged rows with the library's own forward,
- * backward and Adam kernels (device pointers):
- *   X[n_rows][9] features, target[n_rows] wanted log step ratio,
- *   params[4929] in/out, loss_out[epochs] mean weighted-MSE per epoch
- *   (over-predictions weighted by over_weight). */
+/* Y[n_rows] = network(X[n_rows][9]) for the given weights (device). */
+int smol_proposer_forward(const float *params, const float *X, int64_t n_rows,
+                          float *Y, void *stream);
+
+/* Weighted-MSE loss (1/n) sum w (y - target)^2, w = over_weight when
+ * y > target else 1, and its gradient (device float[4865]) over all rows. */
+int smol_proposer_loss_grad(const float *params, const float *X,
+                            const float *target, int64_t n_rows,
+                            float over_weight, float *loss, float *grad,
+                            void *stream);
+
+/* Train in place with the library's forward, backward and Adam kernels
+ * (lr, beta 0.9 / 0.999, eps 1e-8): `epochs` passes over a permutation of
+ * the rows (SplitMix64 Fisher-Yates from `seed`) in minibatches of `batch`
+ * rows.  loss_out (device float[epochs]): mean minibatch loss per epoch. */
 int smol_proposer_train(const float *X, const float *target, int64_t n_rows,
                         float *params, int32_t epochs, int32_t batch,
                         float lr, float over_weight, uint64_t seed,
                         float *loss_out, void *stream);
+
+/* Training rows from a run's per-attempt log (device, rows x 9 doubles as
+ * written by smol_integrate_ex): one row per accepted attempt j that has a
+ * successor, features as above and target
+ *   log(h_{j+1}/h_j) + (1/k) log(err_target / err_{j+1})
+ * (k = embedded order + 1), the ratio that would have hit err = err_target
+ * (0 < err_target <= 1; 0.8 is the default reading) on the next attempt,
+ * clamped.
+ * X (rows x 9) and target (rows) are device buffers of capacity `rows`;
+ * *n_out (host) receives the number of rows written.  Synchronous. */
+int smol_proposer_dataset(const double *log, int64_t rows, int32_t method,
+                          double err_target, float *X, float *target,
+                          int64_t *n_out, void *stream);
 
 /* Timing hook for benchmarks.  Same arguments as smol_rhs (FP64), plus:
  * iters >= 1 launches of each of the three kernels of one right-hand side

@@ -468,18 +468,20 @@ void oracle_moments(int64_t M, const double *n, double *mom)
     }
 }
 
-/* Feature vector of the step proposer: log M0..log M3 of the state, log h,
- * log of the last four weighted error norms (most recent first; entries
- * with no history are 0).  Moments are floored at 1e-300 before the log. */
+/* Feature vector of the step proposer, scaled to O(1) by fixed constants so
+ * that the tanh units start unsaturated: log M0..log M3 of the state / 40,
+ * log h / 10, log of the last four weighted error norms / 10 (most recent
+ * first; entries with no history are 0).  Moments are floored at 1e-300
+ * before the log. */
 void oracle_features(int64_t M, const double *n, double h,
                      const double *err_hist, int32_t n_hist, double *x)
 {
     double mom[4];
     oracle_moments(M, n, mom);
-    for (int k = 0; k < 4; ++k) x[k] = log(fmax(mom[k], 1e-300));
-    x[4] = log(h);
+    for (int k = 0; k < 4; ++k) x[k] = log(fmax(mom[k], 1e-300)) / 40.0;
+    x[4] = log(h) / 10.0;
     for (int q = 0; q < 4; ++q)
-        x[5 + q] = q < n_hist ? log(fmax(err_hist[q], 1e-300)) : 0.0;
+        x[5 + q] = q < n_hist ? log(fmax(err_hist[q], 1e-300)) / 10.0 : 0.0;
 }
 
 #define NIN 9

@@ -21,7 +21,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTEPSIZE, EMAXSTEPS, ENONFINITE, EUNSUPPORTED = \
 METHODS = {"bs3": 0, "bs32": 0, "dp5": 1, "dp54": 1}
 PRECISIONS = {"fp64": 0, "fp32x2": 1}
 CONTROLLERS = {"pi": 0, "learned": 1}
-N_PARAMS = 4929
+N_PARAMS = 4865
 
 _lib = None
 
@@ -54,7 +54,8 @@ class _Instance(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int64), ("R", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("U", ctypes.c_void_p), ("V", ctypes.c_void_p), ("lam", ctypes.c_double),
                 ("n0", ctypes.c_void_p), ("n_out", ctypes.c_void_p), ("t_end", ctypes.c_double),
-                ("rtol", ctypes.c_double), ("atol", ctypes.c_double)]
+                ("rtol", ctypes.c_double), ("atol", ctypes.c_double),
+                ("log", ctypes.c_void_p), ("log_cap", ctypes.c_int64)]
 
 
 def lib():
@@ -73,6 +74,9 @@ def lib():
         L.smol_integrate_batch.argtypes = [i32, ctypes.POINTER(_Instance), i32, i32,
                                            ctypes.POINTER(_Options), ctypes.POINTER(_Stats), vp]
         L.smol_proposer_set.argtypes = [vp, i32, vp]
+        L.smol_proposer_forward.argtypes = [vp, vp, i64, vp, vp]
+        L.smol_proposer_loss_grad.argtypes = [vp, vp, vp, i64, ctypes.c_float, vp, vp, vp]
+        L.smol_proposer_dataset.argtypes = [vp, i64, i32, d, vp, vp, ctypes.POINTER(i64), vp]
         L.smol_proposer_train.argtypes = [vp, vp, i64, vp, i32, i32, ctypes.c_float,
                                           ctypes.c_float, ctypes.c_uint64, vp, vp]
         L.smol_profile_rhs.argtypes = [i64, i32, vp, vp, d, vp, vp, i32,
@@ -210,6 +214,12 @@ def integrate_batch(instances, method="bs3", precision="fp64", **opts):
         arr[i].lam = float(d["lam"])
         arr[i].n0, arr[i].n_out = n0.data_ptr(), out.data_ptr()
         arr[i].t_end, arr[i].rtol, arr[i].atol = float(d["t_end"]), float(d["rtol"]), float(d["atol"])
+        log = d.get("log")
+        if log is not None:
+            _check(log, "log")
+            if log.dim() != 2 or log.shape[1] != 9:
+                raise ValueError("log must be (rows, 9) float64")
+            arr[i].log, arr[i].log_cap = log.data_ptr(), log.shape[0]
     o = _options(**opts)
     st = (_Stats * max(n, 1))()
     with torch.cuda.device(dev):
@@ -224,6 +234,45 @@ def proposer_set(params):
     with torch.cuda.device(params.device):
         _raise(lib().smol_proposer_set(params.data_ptr(), N_PARAMS, _stream(params)),
                "smol_proposer_set")
+
+
+def proposer_forward(params, X):
+    """Network output for each row of X (float32 (n, 9))."""
+    _check(params, "params", dtype=torch.float32, numel=N_PARAMS)
+    _check(X, "X", dtype=torch.float32)
+    Y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    with torch.cuda.device(X.device):
+        _raise(lib().smol_proposer_forward(params.data_ptr(), X.data_ptr(), X.shape[0],
+                                           Y.data_ptr(), _stream(X)), "smol_proposer_forward")
+    return Y
+
+
+def proposer_loss_grad(params, X, target, over_weight=4.0):
+    """(loss, grad) of the weighted MSE over all rows (float32 device tensors)."""
+    _check(params, "params", dtype=torch.float32, numel=N_PARAMS)
+    _check(X, "X", dtype=torch.float32)
+    _check(target, "target", dtype=torch.float32, numel=X.shape[0])
+    loss = torch.zeros(1, dtype=torch.float32, device=X.device)
+    grad = torch.empty(N_PARAMS, dtype=torch.float32, device=X.device)
+    with torch.cuda.device(X.device):
+        _raise(lib().smol_proposer_loss_grad(params.data_ptr(), X.data_ptr(), target.data_ptr(),
+                                             X.shape[0], float(over_weight), loss.data_ptr(),
+                                             grad.data_ptr(), _stream(X)), "smol_proposer_loss_grad")
+    return loss, grad
+
+
+def proposer_dataset(log, rows, method="dp5", err_target=0.8):
+    """(X, target) training rows from the first `rows` rows of a run log."""
+    _check(log, "log")
+    X = torch.empty((max(rows, 1), 9), dtype=torch.float32, device=log.device)
+    tg = torch.empty(max(rows, 1), dtype=torch.float32, device=log.device)
+    n = ctypes.c_int64()
+    with torch.cuda.device(log.device):
+        _raise(lib().smol_proposer_dataset(log.data_ptr(), int(rows), METHODS[method],
+                                           float(err_target), X.data_ptr(),
+                                           tg.data_ptr(), ctypes.byref(n), _stream(log)),
+               "smol_proposer_dataset")
+    return X[: n.value].contiguous(), tg[: n.value].contiguous()
 
 
 def proposer_train(X, target, params, epochs, batch=1024, lr=1e-3, over_weight=4.0, seed=0):

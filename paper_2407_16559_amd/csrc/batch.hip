@@ -190,12 +190,11 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
     if (opts) o = *opts;
     if (o.h0 < 0 || o.h_min < 0 || o.max_steps < 0 || o.log) return SMOL_EINVAL;
     if (o.controller != SMOL_CTRL_PI && o.controller != SMOL_CTRL_LEARNED) return SMOL_EINVAL;
-    if (o.controller != SMOL_CTRL_PI) return SMOL_EUNSUPPORTED;
     for (int i = 0; i < n_inst; ++i) {
         const smol_instance &q = inst[i];
         int rc = check_common(q.M, q.R, q.U, q.V, q.lambda);
         if (rc) return rc;
-        if (!q.n0 || !q.n_out) return SMOL_EINVAL;
+        if (!q.n0 || !q.n_out || (q.log && q.log_cap < 0)) return SMOL_EINVAL;
         if (!(q.rtol > 0) || !(q.atol >= 0) || !(q.t_end >= 0) || !std::isfinite(q.t_end))
             return SMOL_EINVAL;
     }
@@ -207,6 +206,8 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
     DevRoots *roots;
     int rc = get_roots(dev, &roots);
     if (rc) return rc;
+    const float *mlp = proposer_weights(dev);
+    if (o.controller == SMOL_CTRL_LEARNED && !mlp) return SMOL_EINVAL;  // smol_proposer_set first
 
     // ---- sizes and arena layout
     BatchRun br;
@@ -316,6 +317,9 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
             c.max_steps = o.max_steps > 0 ? o.max_steps : 100000000LL;
             c.method = method;
             c.controller = o.controller;
+            c.mlp = o.controller == SMOL_CTRL_LEARNED ? mlp : nullptr;
+            c.log = q.log;
+            c.log_cap = q.log ? q.log_cap : 0;
             c.err_prev = 1.0;
             c.done = q.t_end == 0.0;  // nothing to do: n_out = n0
         }

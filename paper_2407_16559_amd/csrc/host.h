@@ -45,6 +45,7 @@ inline int fft_log2(int64_t M)
 extern SMOL_HIDDEN std::mutex g_mu;
 SMOL_HIDDEN int get_roots(int dev, DevRoots **out);
 SMOL_HIDDEN void stats_from(const IntegCtl &c, smol_stats *st);
+SMOL_HIDDEN const float *proposer_weights(int dev);  // null until smol_proposer_set
 SMOL_HIDDEN int check_common(int64_t M, int32_t R, const double *U, const double *V, double lambda);
 
 // layout conversion kernels (defined in smol.hip)

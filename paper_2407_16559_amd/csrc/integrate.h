@@ -20,6 +20,7 @@
 #define ST_ESTEPSIZE (-4)
 #define ST_EMAXSTEPS (-5)
 #define ST_ENONFINITE (-6)
+#define CTRL_LEARNED 1  // SMOL_CTRL_LEARNED
 
 struct Tableau {
     int S;             // stages including the FSAL stage
@@ -53,6 +54,7 @@ struct IntegCtl {
     int64_t max_steps;
     double *log;
     int64_t log_cap;
+    const float *mlp;  // proposer weights (learned mode)
     int32_t method, controller;
     // dynamic state
     double t, h, t_new, err, err_prev, min_step, h0;
@@ -73,7 +75,6 @@ struct IntegDev {
     void *Z, *Qp;
     double *red_part, *red, *epart;
     Roots rt;
-    const float *mlp;  // proposer weights (may be null)
 };
 
 __device__ __forceinline__ RhsPlanDev plan_of(const IntegDev &I, const IntegCtl &c)
@@ -190,7 +191,7 @@ __device__ inline void prepare_attempt(IntegCtl &c, bool new_step)
 }
 
 // Deterministic block reduction of epart rows (fixed strided order, then a
-// fixed tree); thread 0 receives the totals.
+// fixed tree); every thread receives the totals.
 __device__ inline void block_sum_epart(const double *ep, int njobs, double *tot)
 {
     __shared__ double sh[SMOL_WG][SMOL_EPART];
@@ -206,8 +207,61 @@ __device__ inline void block_sum_epart(const double *ep, int njobs, double *tot)
             for (int q = 0; q < SMOL_EPART; ++q) sh[tid][q] += sh[tid + off][q];
         __syncthreads();
     }
-    if (tid == 0)
-        for (int q = 0; q < SMOL_EPART; ++q) tot[q] = sh[0][q];
+    for (int q = 0; q < SMOL_EPART; ++q) tot[q] = sh[0][q];
+    __syncthreads();
+}
+
+// ---- learned step proposer ----------------------------------------------
+// 9-64-64-1 tanh MLP, FP32, parameters W1[64][9], b1[64], W2[64][64], b2[64],
+// W3[64], b3 (4865 floats).  Output: log(h_next / h).
+#define MLP_NIN 9
+#define MLP_NH 64
+#define MLP_OFF_B1 (MLP_NH * MLP_NIN)
+#define MLP_OFF_W2 (MLP_OFF_B1 + MLP_NH)
+#define MLP_OFF_B2 (MLP_OFF_W2 + MLP_NH * MLP_NH)
+#define MLP_OFF_W3 (MLP_OFF_B2 + MLP_NH)
+#define MLP_OFF_B3 (MLP_OFF_W3 + MLP_NH)
+#define MLP_NPARAM (MLP_OFF_B3 + 1)
+#define MLP_LOG_FMIN (-1.6094379124341003)  // log 0.2
+#define MLP_LOG_FMAX (2.302585092994046)    // log 10
+
+// Features: log-moments of the new state / 40, log h / 10, log of the last
+// four error norms (most recent first, missing ones 0) / 10.
+__device__ __forceinline__ void proposer_features(const double *mom, double h, const double *hist,
+                                                  int nh, float *x)
+{
+    for (int k = 0; k < 4; ++k) x[k] = (float)(log(fmax(mom[k], 1e-300)) / 40.0);
+    x[4] = (float)(log(h) / 10.0);
+    for (int q = 0; q < 4; ++q) x[5 + q] = q < nh ? (float)(log(fmax(hist[q], 1e-300)) / 10.0) : 0.0f;
+}
+
+// Forward pass by a whole workgroup (fixed summation order); every thread
+// receives the output.
+__device__ inline float mlp_forward_block(const float *p, const float *x)
+{
+    __shared__ float h1[MLP_NH], h2[MLP_NH], y;
+    const int tid = threadIdx.x;
+    if (tid < MLP_NH) {
+        float z = p[MLP_OFF_B1 + tid];
+        for (int i = 0; i < MLP_NIN; ++i) z = fmaf(p[tid * MLP_NIN + i], x[i], z);
+        h1[tid] = tanhf(z);
+    }
+    __syncthreads();
+    if (tid < MLP_NH) {
+        float z = p[MLP_OFF_B2 + tid];
+        for (int i = 0; i < MLP_NH; ++i) z = fmaf(p[MLP_OFF_W2 + tid * MLP_NH + i], h1[i], z);
+        h2[tid] = tanhf(z);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        float z = p[MLP_OFF_B3];
+        for (int i = 0; i < MLP_NH; ++i) z = fmaf(p[MLP_OFF_W3 + i], h2[i], z);
+        y = z;
+    }
+    __syncthreads();
+    const float out = y;
+    __syncthreads();
+    return out;
 }
 
 __device__ __forceinline__ double rms_of(double sumsq, int64_t M) { return sqrt(sumsq / (double)M); }
@@ -265,22 +319,45 @@ __device__ inline void init_h_step(const IntegDev &I, int njobs)
     prepare_attempt(c, true);
 }
 
-// Accept / reject and the next step size (PI controller), after the last
-// stage; run by one whole workgroup.
+// Accept / reject and the next step size after the last stage; run by one
+// whole workgroup.  PI control, or (learned mode) the proposer's
+// log(h_next/h) after an accepted step that did not follow a rejection,
+// with PI as the fallback after a rejection or for non-finite features.
 __device__ inline void controller_step(const IntegDev &I, int njobs)
 {
     IntegCtl &c = *I.ctl;
     if (c.done) return;
     double tot[SMOL_EPART];
     block_sum_epart(I.epart, njobs, tot);
-    if (threadIdx.x) return;
     const Tableau &T = c_tab[c.method];
     const int k = T.q + 1;
     const double err = rms_of(tot[0], I.M);
+    const bool accept = err <= 1.0;
+    const bool bad = isnan(err) || tot[5] > 0.0;
+    // error history including this attempt (most recent first)
+    double hist[4] = {err, c.err_hist[0], c.err_hist[1], c.err_hist[2]};
+    const int nh = c.n_hist < 3 ? c.n_hist + 1 : 4;
+    bool learned = false;
+    double dlog = 0.0;
+    if (c.controller == CTRL_LEARNED && c.mlp && accept && !bad && !c.rejected) {
+        float x[MLP_NIN];
+        proposer_features(tot + 1, c.h, hist, nh, x);
+        bool finite = true;
+        for (int q = 0; q < MLP_NIN; ++q) finite = finite && isfinite(x[q]);
+        if (finite) {
+            const float y = mlp_forward_block(c.mlp, x);
+            if (isfinite(y)) {
+                learned = true;
+                dlog = fmin(fmax((double)y, MLP_LOG_FMIN), MLP_LOG_FMAX);
+            }
+        }
+    }
+    if (threadIdx.x) return;
     c.err = err;
     c.attempts += 1;
     c.n_rhs += T.S - 1;
-    const bool accept = err <= 1.0;
+    for (int q = 0; q < 4; ++q) c.err_hist[q] = hist[q];
+    c.n_hist = nh;
     if (c.log && c.attempts <= c.log_cap) {
         double *row = c.log + (c.attempts - 1) * 9;
         row[0] = c.t;
@@ -294,20 +371,25 @@ __device__ inline void controller_step(const IntegDev &I, int njobs)
         row[8] = tot[4];
     }
     // a NaN norm or a non-finite new state ends the run (state kept)
-    if (isnan(err) || tot[5] > 0.0) {
+    if (bad) {
         c.status = ST_ENONFINITE;
         c.done = 1;
         return;
     }
     if (accept) {
         double fac;
-        if (err == 0.0)
-            fac = c.facmax;
-        else
-            fac = c.safety * pow(err, -c.alpha) * pow(c.err_prev, c.beta);
+        if (learned) {
+            fac = exp(dlog);
+        } else {
+            if (c.controller == CTRL_LEARNED) c.n_fallback += 1;
+            if (err == 0.0)
+                fac = c.facmax;
+            else
+                fac = c.safety * pow(err, -c.alpha) * pow(c.err_prev, c.beta);
+            if (c.rejected && fac > 1.0) fac = 1.0;
+        }
         if (fac > c.facmax) fac = c.facmax;
         if (fac < c.facmin) fac = c.facmin;
-        if (c.rejected && fac > 1.0) fac = 1.0;
         c.err_prev = fmax(err, 1e-4);
         c.t = c.t_new;
         c.h = c.h * fac;

@@ -358,7 +358,6 @@ IntegDev integ_dev(const Plan *p, const DevRoots *r)
     I.epart = p->epart;
     I.rt.tw = r->tw;
     I.rt.fine = r->fine;
-    I.mlp = nullptr;
     return I;
 }
 
@@ -490,7 +489,6 @@ extern "C" int smol_integrate_ex(int64_t M, int32_t R, const double *U, const do
     if (opts) o = *opts;
     if (o.h0 < 0 || o.h_min < 0 || o.max_steps < 0 || (o.log && o.log_cap < 0)) return SMOL_EINVAL;
     if (o.controller != SMOL_CTRL_PI && o.controller != SMOL_CTRL_LEARNED) return SMOL_EINVAL;
-    if (o.controller != SMOL_CTRL_PI) return SMOL_EUNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     if (stats) memset(stats, 0, sizeof(*stats));
     if (t_end == 0.0) {
@@ -534,6 +532,10 @@ extern "C" int smol_integrate_ex(int64_t M, int32_t R, const double *U, const do
     c.method = method;
     c.controller = o.controller;
     c.err_prev = 1.0;
+    if (o.controller == SMOL_CTRL_LEARNED) {
+        c.mlp = proposer_weights(p->dev);
+        if (!c.mlp) return SMOL_EINVAL;  // smol_proposer_set first
+    }
     HIP_TRY(hipMemcpyAsync(p->ctl, &c, sizeof(c), hipMemcpyHostToDevice, s));
     // the integrator keeps every vector in the transposed layout
     hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, U, I.Ut, M, R, M, I.Mt, p->logL);
@@ -657,10 +659,3 @@ extern "C" int smol_profile_rhs(int64_t M, int32_t R, const double *U, const dou
     return SMOL_OK;
 }
 
-// ---- entry points not built yet ------------------------------------------
-extern "C" int smol_proposer_set(const float *, int32_t, void *) { return SMOL_EUNSUPPORTED; }
-extern "C" int smol_proposer_train(const float *, const float *, int64_t, float *, int32_t,
-                                   int32_t, float, float, uint64_t, float *, void *)
-{
-    return SMOL_EUNSUPPORTED;
-}

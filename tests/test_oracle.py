@@ -321,13 +321,16 @@ def test_integrate_ends_exactly_at_t_end():
 # ---------------------------------------------------------------------------
 
 def test_features_on_closed_form():
-    """Moments of the closed-form state: M0 = 1/(1+t/2), M1 = 1."""
+    """Moments of the closed-form state: M0 = 1/(1+t/2), M1 = 1, and
+    M2 = 1 + t (second moment of the K == 1 solution from e_1); features
+    are the logs scaled by 1/40 (moments) and 1/10 (step, errors)."""
     t = 3.0
-    n = closed_form(256, t)
+    n = closed_form(512, t)
     x = oracle.features(n, 0.25, [0.5, 0.25])
-    np.testing.assert_allclose(x[0], -np.log1p(t / 2), rtol=1e-12)
+    np.testing.assert_allclose(40 * x[0], -np.log1p(t / 2), rtol=1e-12)
     assert abs(x[1]) < 1e-12
-    np.testing.assert_allclose(x[4:7], np.log([0.25, 0.5, 0.25]), rtol=1e-14)
+    np.testing.assert_allclose(40 * x[2], np.log1p(t), rtol=1e-10)
+    np.testing.assert_allclose(10 * x[4:7], np.log([0.25, 0.5, 0.25]), rtol=1e-14)
     assert x[7] == 0.0 and x[8] == 0.0
 
 
