@@ -56,8 +56,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--t-end", type=float, default=None, help="shorter runs (profiling)")
-    ap.add_argument("--workload", choices=["single", "batch"], default="single",
-                    help="single: the M=65536 DP5 instance (default); batch: the 256-instance sweep")
+    ap.add_argument("--workload", choices=["single", "batch", "learned"], default="single",
+                    help="single: the M=65536 DP5 instance (default); batch: the 256-instance "
+                         "sweep; learned: train the step proposer, then learned vs PI at M=262144")
+    ap.add_argument("--no-accuracy-check", action="store_true",
+                    help="skip the tight reference run that selects rtol (profiling)")
+    ap.add_argument("--train-instances", type=int, default=128)
+    ap.add_argument("--epochs", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -73,6 +78,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == "batch":
         return bench_batch(args, smol, W, torch, dev)
+    if args.workload == "learned":
+        return bench_learned(args, smol, W, torch, dev)
     c = W.CONFIGS[2]
     t_end = args.t_end if args.t_end else c["t_end"]
     U, V, lam, n0 = W.config_instance(2)
@@ -82,10 +89,24 @@ def main():
     n0d = torch.from_numpy(n0).to(dev)
     out = torch.empty_like(n0d)
 
-    def run():
-        return smol.integrate(Ud, Vd, lam, n0d, t_end, c["rtol"], c["atol"], method="dp5",
-                              out=out, raise_on_error=True)
+    def run(rtol=None, atol=None):
+        return smol.integrate(Ud, Vd, lam, n0d, t_end, rtol or c["rtol"], atol or c["atol"],
+                              method="dp5", out=out, raise_on_error=True)
 
+    # time-to-t_end "at 1e-6 relative error": the loosest rtol in
+    # 1e-6, 3e-7, 1e-7, ... whose end state is within 1e-6 (max-norm,
+    # relative) of a tight run (rtol 1e-10, atol 1e-16); untimed
+    rtol, err_tight = c["rtol"], None
+    if not args.no_accuracy_check:
+        ref = run(1e-10, 1e-16)[0].clone()
+        for rtol in (1e-6, 3e-7, 1e-7, 3e-8, 1e-8):
+            got = run(rtol)[0]
+            err_tight = ((got - ref).abs().max() / ref.abs().max()).item()
+            if err_tight <= 1e-6:
+                break
+        print(f"bench: rtol {rtol:g}, error vs tight run {err_tight:.2e}", file=sys.stderr,
+              flush=True)
+    c = dict(c, rtol=rtol)
     for _ in range(args.warmup):
         run()
     torch.cuda.synchronize()
@@ -127,10 +148,12 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "single-large-oscillatory: M=65536, R=3 kernel (i/j)^a+(j/i)^a+2, "
-                               f"a=0.45, lam=0.005, monodisperse start, DP5(4) PI, rtol=1e-6, "
-                               f"atol=1e-12, t_end={t_end:g}",
+                               f"a=0.45, lam=0.005, monodisperse start, DP5(4) PI, "
+                               f"rtol={c['rtol']:g}, atol=1e-12, t_end={t_end:g}",
                    "M": M, "R": R, "fft_length": L, "parallelism": "1 GPU"},
         "time_to_t_end_s": elapsed / args.steps,
+        "rtol": c["rtol"],
+        "rel_err_vs_tight_run": err_tight,
         "accepted_steps_per_run": stats[-1]["n_accept"],
         "rejected_steps_per_run": stats[-1]["n_reject"],
         "rhs_evals_per_s": n_rhs / elapsed,
@@ -189,6 +212,97 @@ def bench_batch(args, smol, W, torch, dev):
         "accepted_steps_total": n_acc,
         "max_accepted_steps_one_instance": max(s["n_accept"] for s in stats),
         "all_ok": all(s["status"] == 0 for s in stats),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_learned(args, smol, W, torch, dev):
+    """Learned step proposer against PI on the large instance (M = 262144,
+    a = 0.4, lam = 0.01, monodisperse start, DP5(4), rtol 1e-6, t_end 1e4).
+
+    Training data: per-attempt logs of PI runs (DP5, rtol 1e-6, t_end 1e4) on
+    instances drawn from the batched sweep's distribution (seed 1), run as one
+    batch; hindsight targets for err = 0.8; weighted-MSE training with Adam
+    (lr 1e-3, overshoot weight 4) from seed-12345 initial weights, all in the
+    library's kernels.  Then one run with each controller, timed, and both
+    compared with a tight run (rtol 1e-10, atol 1e-16)."""
+    import numpy as np
+    c = W.CONFIGS[5]
+    t_end = args.t_end if args.t_end else c["t_end"]
+    cap = 40000
+    draws = W.batch_draws(args.train_instances, seed=1)
+    Xs, Ts = [], []
+    t_runs = 0.0
+    for lo in range(0, len(draws), 128):
+        insts, logs = [], []
+        for d in draws[lo:lo + 128]:
+            U, V, lam, n0 = W.batch_instance(d)
+            log = torch.zeros((cap, 9), dtype=torch.float64, device=dev)
+            insts.append(dict(U=torch.from_numpy(U).to(dev), V=torch.from_numpy(V).to(dev),
+                              lam=lam, n0=torch.from_numpy(n0).to(dev), t_end=t_end,
+                              rtol=c["rtol"], atol=c["atol"], log=log))
+            logs.append(log)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, stats = smol.integrate_batch(insts, method="dp5")
+        torch.cuda.synchronize()
+        t_runs += time.perf_counter() - t0
+        for log, st in zip(logs, stats):
+            X, tg = smol.proposer_dataset(log, min(cap, st["n_accept"] + st["n_reject"]), "dp5",
+                                          0.8)
+            Xs.append(X)
+            Ts.append(tg)
+        print(f"bench: training runs {lo + len(insts)}/{len(draws)} ({t_runs:.1f} s)",
+              file=sys.stderr, flush=True)
+        del insts, logs
+    X = torch.cat(Xs).contiguous()
+    tg = torch.cat(Ts).contiguous()
+    params = torch.from_numpy(W.mlp_init(12345).astype(np.float32)).to(dev)
+    t0 = time.perf_counter()
+    loss = smol.proposer_train(X, tg, params, epochs=args.epochs, batch=1024, lr=1e-3,
+                               over_weight=4.0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    print(f"bench: trained on {X.shape[0]} rows in {t_train:.1f} s, loss "
+          f"{loss[0].item():.4f} -> {loss[-1].item():.4f}", file=sys.stderr, flush=True)
+    smol.proposer_set(params)
+
+    U, V = W.brownian_rank3(c["M"], c["a"])
+    Ud, Vd = torch.from_numpy(U).to(dev), torch.from_numpy(V).to(dev)
+    n0d = torch.from_numpy(W.monodisperse(c["M"])).to(dev)
+    ref, _ = smol.integrate(Ud, Vd, c["lam"], n0d, t_end, 1e-10, 1e-16, method="dp5",
+                            raise_on_error=True)
+    res = {}
+    for ctrl in ("pi", "learned"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out, st = smol.integrate(Ud, Vd, c["lam"], n0d, t_end, c["rtol"], c["atol"],
+                                 method="dp5", controller=ctrl, raise_on_error=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        err = ((out - ref).abs().max() / ref.abs().max()).item()
+        res[ctrl] = {"time_to_t_end_s": dt, "n_accept": st["n_accept"],
+                     "n_reject": st["n_reject"], "n_rhs": st["n_rhs"],
+                     "reject_rate": st["n_reject"] / max(1, st["n_accept"] + st["n_reject"]),
+                     "n_fallback": st["n_fallback"], "rel_err_vs_tight_run": err}
+        print(f"bench: {ctrl}: {res[ctrl]}", file=sys.stderr, flush=True)
+    line = {
+        "metric": "time-to-t_end with the learned step proposer, M=2^18 R=3",
+        "value": res["learned"]["time_to_t_end_s"],
+        "unit": "s",
+        "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": 1e3 * res["learned"]["time_to_t_end_s"],
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (network f32)", "data": "synthetic",
+        "config": {"workload": f"learned-proposer: M=262144, R=3, a=0.4, lam=0.01, monodisperse, "
+                               f"DP5(4), rtol=1e-6, atol=1e-12, t_end={t_end:g}; trained on "
+                               f"{len(draws)} sweep-distributed runs", "parallelism": "1 GPU"},
+        "learned": res["learned"], "pi": res["pi"],
+        "speedup_vs_pi": res["pi"]["time_to_t_end_s"] / res["learned"]["time_to_t_end_s"],
+        "rhs_ratio_vs_pi": res["learned"]["n_rhs"] / res["pi"]["n_rhs"],
+        "training": {"runs_s": t_runs, "rows": int(X.shape[0]), "epochs": args.epochs,
+                     "train_s": t_train, "loss_first": loss[0].item(),
+                     "loss_last": loss[-1].item()},
     }
     print(json.dumps(line), flush=True)
 

@@ -225,6 +225,42 @@ int smol_profile_rhs(int64_t M, int32_t R, const double *U, const double *V,
                      double lambda, const double *n, double *dndt,
                      int32_t iters, float *ms_out, void *stream);
 
+/* Launch schedules.  Each of the three right-hand-side kernels (column
+ * pass A, row-pair pass B, inverse column pass + finish C) comes in up to
+ * four variants that differ in the radix of the in-register butterflies and
+ * in the workgroup tile; the results agree to rounding (FFT normwise error
+ * O(eps log L)) but are not bitwise equal across variants:
+ *   variant & 1: 8 waves (512 threads) per workgroup instead of 4;
+ *   variant & 2: 4 complex values per lane (radix-4 stages) instead of 8
+ *                (16 for 1024-point transforms); only for transforms of
+ *                length <= 256.
+ * Variants 1..3 exist for FP64 and L = 2^logL >= 2^12 only; float-float
+ * plans always use variant 0.  The schedule is process-wide per logL and
+ * starts from a table tuned on MI355X.
+ *
+ * smol_set_schedule: variants (HOST, 3 ints: A, B, C) for transforms of
+ * length 2^logL, 6 <= logL <= 20; EINVAL for a variant that does not exist
+ * at that length.  Existing plans switch at their next call (captured step
+ * graphs are rebuilt).  smol_get_schedule: the current variants. */
+int smol_set_schedule(int32_t logL, const int32_t *variants);
+int smol_get_schedule(int32_t logL, int32_t *variants);
+
+/* Autotuner: times step attempts of the caller's instance (same arguments
+ * as smol_integrate: U, V, n0 device arrays; method SMOL_BS32 or
+ * SMOL_DP54; FP64) under candidate schedules of its transform length,
+ * `attempts` attempts per run, best of `reps` runs after one untimed run,
+ * and descends over the kernels (C, then B, then A), keeping a variant only
+ * if it saves at least 2 %.  The chosen schedule is installed (as by
+ * smol_set_schedule) and written to variants_out (HOST, 3 ints);
+ * ms_out (HOST, 2 floats, may be null) receives the milliseconds per
+ * attempt of the starting schedule and of the chosen one.
+ * Allocates one M-vector of scratch for the duration of the call.
+ * Synchronous. */
+int smol_autotune(int64_t M, int32_t R, const double *U, const double *V,
+                  double lambda, const double *n0, int32_t method,
+                  int32_t attempts, int32_t reps, int32_t *variants_out,
+                  float *ms_out, void *stream);
+
 /* Free cached plans and workspaces on the current device. */
 int smol_release_plans(void);
 

@@ -81,6 +81,10 @@ def lib():
                                           ctypes.c_float, ctypes.c_uint64, vp, vp]
         L.smol_profile_rhs.argtypes = [i64, i32, vp, vp, d, vp, vp, i32,
                                        ctypes.POINTER(ctypes.c_float), vp]
+        L.smol_set_schedule.argtypes = [i32, ctypes.POINTER(i32)]
+        L.smol_get_schedule.argtypes = [i32, ctypes.POINTER(i32)]
+        L.smol_autotune.argtypes = [i64, i32, vp, vp, d, vp, i32, i32, i32, ctypes.POINTER(i32),
+                                    ctypes.POINTER(ctypes.c_float), vp]
         L.smol_release_plans.argtypes = []
         L.smol_strerror.argtypes = [ctypes.c_int]
         L.smol_strerror.restype = ctypes.c_char_p
@@ -306,6 +310,33 @@ def profile_rhs(U, V, lam, n, iters=50, out=None):
                                     out.data_ptr(), int(iters), ms, _stream(n))
     _raise(rc, "smol_profile_rhs")
     return {"phase_a": ms[0], "phase_b": ms[1], "phase_c": ms[2], "rhs": ms[3]}
+
+
+def set_schedule(logL, variants):
+    """Kernel variants (A, B, C) for transforms of length 2^logL (FP64)."""
+    v = (ctypes.c_int32 * 3)(*[int(x) for x in variants])
+    _raise(lib().smol_set_schedule(int(logL), v), "smol_set_schedule")
+
+
+def get_schedule(logL):
+    v = (ctypes.c_int32 * 3)()
+    _raise(lib().smol_get_schedule(int(logL), v), "smol_get_schedule")
+    return tuple(v)
+
+
+def autotune(U, V, lam, n0, method="dp5", attempts=64, reps=3):
+    """Tune the schedule of n0's transform length on this instance; returns
+    (variants, ms per step attempt before, ms per step attempt after)."""
+    _check(n0, "n0")
+    M = n0.numel()
+    U, V, R = _factors(U, V, M)
+    v = (ctypes.c_int32 * 3)()
+    ms = (ctypes.c_float * 2)()
+    with torch.cuda.device(n0.device):
+        _raise(lib().smol_autotune(M, R, U.data_ptr(), V.data_ptr(), float(lam), n0.data_ptr(),
+                                   METHODS[method], int(attempts), int(reps), v, ms,
+                                   _stream(n0)), "smol_autotune")
+    return tuple(v), ms[0], ms[1]
 
 
 def release_plans():

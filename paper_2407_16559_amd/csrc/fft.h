@@ -40,15 +40,24 @@ __device__ __forceinline__ double im_d(cff v) { return ff_to(v.y); }
 
 constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
 
-template <int N>
+// Elements per lane: the radix of the in-register butterflies.  8 by
+// default (16 at N = 1024, where a transform must fit one wave); 4 and 16
+// are the alternatives a schedule may pick (G = N/E lanes must fit a wave).
+constexpr int fft_default_e(int N) { return N == 1024 ? 16 : 8; }
+constexpr bool fft_valid_e(int N, int E)
+{
+    return (E == 4 || E == 8 || E == 16) && E <= N && N / E <= 64;
+}
+
+template <int N, int E_ = fft_default_e(N)>
 struct FftShape {
     static_assert(N >= 8 && N <= 1024 && (N & (N - 1)) == 0, "FFT length");
-    static constexpr int LOGN = (N == 8) ? 3 : (N == 16) ? 4 : (N == 32) ? 5 : (N == 64) ? 6
-                              : (N == 128) ? 7 : (N == 256) ? 8 : (N == 512) ? 9 : 10;
-    static constexpr int E = (N == 1024) ? 16 : 8;  // elements per lane
+    static_assert(fft_valid_e(N, E_), "elements per lane");
+    static constexpr int LOGN = ilog2c(N);
+    static constexpr int E = E_;                    // elements per lane
     static constexpr int G = N / E;                 // lanes per transform
     static constexpr int B = 64 / G;                // transforms per wave
-    static constexpr int LOGE = (E == 16) ? 4 : 3;
+    static constexpr int LOGE = ilog2c(E);
     // stage radices: E repeated, then one smaller radix for the remainder
     static constexpr int NFULL = LOGN / LOGE;
     static constexpr int REM = LOGN % LOGE;
@@ -156,9 +165,9 @@ __device__ __forceinline__ void pow_tree(C w, C (&o)[R])
 // Per-lane base twiddles of every stage after the first, W_{Ns r}^k with
 // k = j mod Ns, loaded once before the data arrives (split into float-float
 // from the FP64 table when C = cff).
-template <int N, bool INV, class C>
+template <int N, bool INV, class C, int E = fft_default_e(N)>
 struct FftTw {
-    using S = FftShape<N>;
+    using S = FftShape<N, E>;
     static constexpr int PMAX = (S::E / 2 > 0) ? S::E / 2 : 1;
     C w[S::NST > 1 ? S::NST - 1 : 1][PMAX];
 
@@ -181,10 +190,11 @@ struct FftTw {
     }
 };
 
-template <int N, bool INV, int ST, class C>
+template <int N, bool INV, int ST, class C, int E = fft_default_e(N)>
 struct FftStage {
-    using S = FftShape<N>;
-    __device__ __forceinline__ static void run(C (&v)[S::E], C *buf, int g, const FftTw<N, INV, C> &tw)
+    using S = FftShape<N, E>;
+    __device__ __forceinline__ static void run(C (&v)[S::E], C *buf, int g,
+                                               const FftTw<N, INV, C, E> &tw)
     {
         constexpr int r = S::radix(ST);
         constexpr int LR = ilog2c(r);
@@ -224,18 +234,17 @@ struct FftStage {
 #pragma unroll
                 for (int q = 0; q < r; ++q) buf[base + q * Ns] = v[p + q * P];
             }
-            FftStage<N, INV, ST + 1, C>::run(v, buf, g, tw);
+            FftStage<N, INV, ST + 1, C, E>::run(v, buf, g, tw);
         }
     }
 };
 
 // Transform the N values held by lanes g = 0..G-1 (layout above) in place.
 // buf: this transform's LDS region (N entries); tw: loaded base twiddles.
-template <int N, bool INV, class C>
-__device__ __forceinline__ void wave_fft(C (&v)[FftShape<N>::E], C *buf, int g,
-                                         const FftTw<N, INV, C> &tw)
+template <int N, bool INV, class C, int E>
+__device__ __forceinline__ void wave_fft(C (&v)[E], C *buf, int g, const FftTw<N, INV, C, E> &tw)
 {
-    FftStage<N, INV, 0, C>::run(v, buf, g, tw);
+    FftStage<N, INV, 0, C, E>::run(v, buf, g, tw);
 }
 
 // Lane's four-step twiddles W_L^{e (g + i G)}, i = 0..E-1, from two table

@@ -1,0 +1,160 @@
+// Kernels of the three right-hand-side phases, per transform shape
+// (N1 x N2), complex arithmetic T and schedule variant (E elements per
+// lane, W waves per workgroup), and their launch functors.  Included only by
+// the phase translation units, so each kernel is compiled once.
+#pragma once
+#include "sched.h"
+
+// Map workgroup b to a logical index so that consecutive logical indices land
+// on the same XCD (workgroups are dealt round-robin over the 8 XCDs).
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    if (nb % 8) return b;
+    return (b % 8) * (nb / 8) + b / 8;
+}
+
+// ---- plain right-hand side -------------------------------------------------
+
+template <int N1, int N2, class T, int E, int W>
+__global__ __launch_bounds__(64 * W) void k_phaseA(RhsPlanDev P, Pro in, int nunits)
+{
+    extern __shared__ cd lds[];
+    const int unit = xcd_remap(blockIdx.x, gridDim.x);
+    if (unit < nunits) PhaseA<N1, N2, T, E, W>::run(P, in, unit, (T *)lds);
+}
+
+template <int N1, int N2, class T, int E, int W>
+__global__ __launch_bounds__(64 * W) void k_phaseB(RhsPlanDev P, int red_jobs)
+{
+    extern __shared__ cd lds[];
+    const int u = blockIdx.x;
+    if (u == PhaseB<N1, N2, T, E, W>::units()) {
+        if (red_jobs > 0) finalize_reductions<64 * W>(P, red_jobs);
+        return;
+    }
+    PhaseB<N1, N2, T, E, W>::run(P, u, (T *)lds);
+}
+
+template <int N1, int N2, class T, int E, int W>
+__global__ __launch_bounds__(64 * W) void k_phaseC(RhsPlanDev P, Epi ep, int nunits)
+{
+    extern __shared__ cd lds[];
+    const int unit = xcd_remap(blockIdx.x, gridDim.x);
+    if (unit < nunits) PhaseC<N1, N2, T, E, W>::template run<false>(P, ep, unit, (T *)lds);
+}
+
+// ---- integrator stages: the same phases, buffers from the control block ----
+
+template <int N1, int N2, class T, int E, int W>
+__global__ __launch_bounds__(64 * W) void k_int_A(IntegDev I, int stage, int nunits)
+{
+    const IntegCtl &c = *I.ctl;
+    if (c.done) return;
+    extern __shared__ cd lds[];
+    const Tableau &tab = c_tab[c.method];
+    const RhsPlanDev P = plan_of(I, c);
+    const Pro in = stage_pro(I, c, tab, stage);
+    const int unit = xcd_remap(blockIdx.x, gridDim.x);
+    if (unit < nunits) PhaseA<N1, N2, T, E, W>::run(P, in, unit, (T *)lds);
+}
+
+// jobs_a / jobs_c: reduction partial rows written by the column pass (stages
+// 0..2) or by the previous stage's fused finish (later stages).
+template <int N1, int N2, class T, int E, int W>
+__global__ __launch_bounds__(64 * W) void k_int_B(IntegDev I, int stage, int jobs_a, int jobs_c)
+{
+    const IntegCtl &c = *I.ctl;
+    if (c.done) return;
+    extern __shared__ cd lds[];
+    const RhsPlanDev P = plan_of(I, c);
+    const int u = blockIdx.x;
+    if (u == PhaseB<N1, N2, T, E, W>::units()) {
+        finalize_reductions<64 * W>(P, stage <= 2 ? jobs_a : jobs_c);
+        return;
+    }
+    PhaseB<N1, N2, T, E, W>::run(P, u, (T *)lds);
+}
+
+template <int N1, int N2, class T, int E, int W, bool FUSE>
+__global__ __launch_bounds__(64 * W) void k_int_C(IntegDev I, int stage, int nunits)
+{
+    const IntegCtl &c = *I.ctl;
+    if (c.done) return;
+    extern __shared__ cd lds[];
+    const Tableau &tab = c_tab[c.method];
+    const RhsPlanDev P = plan_of(I, c);
+    const Epi ep = stage_epi(I, c, tab, stage);
+    const int unit = xcd_remap(blockIdx.x, gridDim.x);
+    if (unit < nunits) PhaseC<N1, N2, T, E, W>::template run<FUSE>(P, ep, unit, (T *)lds);
+}
+
+// ---- launch functors (used through with_variant) ----------------------------
+
+struct RhsA {
+    template <int N1, int N2, class T, int E, int W>
+    static int run(const RhsPlanDev &P, const Pro &in, hipStream_t s)
+    {
+        using A = PhaseA<N1, N2, T, E, W>;
+        const int n = A::units(P.R);
+        hipLaunchKernelGGL((k_phaseA<N1, N2, T, E, W>), dim3(n), dim3(A::NT), sizeof(cd) * A::LDS,
+                           s, P, in, n);
+        return SMOL_OK;
+    }
+};
+struct RhsB {
+    template <int N1, int N2, class T, int E, int W>
+    static int run(const RhsPlanDev &P, int red_jobs, hipStream_t s)
+    {
+        using B = PhaseB<N1, N2, T, E, W>;
+        hipLaunchKernelGGL((k_phaseB<N1, N2, T, E, W>), dim3(B::units() + 1), dim3(B::NT),
+                           sizeof(cd) * B::LDS, s, P, red_jobs);
+        return SMOL_OK;
+    }
+};
+struct RhsC {
+    template <int N1, int N2, class T, int E, int W>
+    static int run(const RhsPlanDev &P, const Epi &ep, hipStream_t s)
+    {
+        using C = PhaseC<N1, N2, T, E, W>;
+        const int n = C::units();
+        hipLaunchKernelGGL((k_phaseC<N1, N2, T, E, W>), dim3(n), dim3(C::NT), sizeof(cd) * C::LDS,
+                           s, P, ep, n);
+        return SMOL_OK;
+    }
+};
+struct IntA {
+    template <int N1, int N2, class T, int E, int W>
+    static int run(const IntegDev &I, int stage, hipStream_t s)
+    {
+        using A = PhaseA<N1, N2, T, E, W>;
+        const int n = A::units(I.R);
+        hipLaunchKernelGGL((k_int_A<N1, N2, T, E, W>), dim3(n), dim3(A::NT), sizeof(cd) * A::LDS,
+                           s, I, stage, n);
+        return SMOL_OK;
+    }
+};
+struct IntB {
+    template <int N1, int N2, class T, int E, int W>
+    static int run(const IntegDev &I, int stage, int jobs_a, int jobs_c, hipStream_t s)
+    {
+        using B = PhaseB<N1, N2, T, E, W>;
+        hipLaunchKernelGGL((k_int_B<N1, N2, T, E, W>), dim3(B::units() + 1), dim3(B::NT),
+                           sizeof(cd) * B::LDS, s, I, stage, jobs_a, jobs_c);
+        return SMOL_OK;
+    }
+};
+struct IntC {
+    template <int N1, int N2, class T, int E, int W>
+    static int run(const IntegDev &I, int stage, bool fuse, hipStream_t s)
+    {
+        using C = PhaseC<N1, N2, T, E, W>;
+        const int n = C::units();
+        if (fuse)
+            hipLaunchKernelGGL((k_int_C<N1, N2, T, E, W, true>), dim3(n), dim3(C::NT),
+                               sizeof(cd) * C::LDS_FUSE, s, I, stage, n);
+        else
+            hipLaunchKernelGGL((k_int_C<N1, N2, T, E, W, false>), dim3(n), dim3(C::NT),
+                               sizeof(cd) * C::LDS, s, I, stage, n);
+        return SMOL_OK;
+    }
+};

@@ -100,12 +100,13 @@ struct Epi {
     double *epart;          // C_LAST / C_INIT*: [jobs][SMOL_EPART]
 };
 
-// Sum per-wave values sh[w][0..nq) over the waves in order (after a barrier).
+// Sum per-wave values sh[w][0..nq) over the W waves in order (after a barrier).
+template <int W = SMOL_WAVES>
 __device__ __forceinline__ double sum_waves(const double *sh, int nq, int q)
 {
     double a = 0.0;
 #pragma unroll
-    for (int w = 0; w < SMOL_WAVES; ++w) a += sh[w * nq + q];
+    for (int w = 0; w < W; ++w) a += sh[w * nq + q];
     return a;
 }
 
@@ -129,21 +130,23 @@ __device__ __forceinline__ cff div4i(cff x) { return cff{ff_scale2(x.y, 0.25f), 
 // Phase A
 // --------------------------------------------------------------------------
 
-template <int N1, int N2, class C>
+// E: elements per lane of the column transforms; W: waves per workgroup.
+template <int N1, int N2, class C, int E = fft_default_e(N1), int W = SMOL_WAVES>
 struct PhaseA {
-    using F = FftShape<N1>;
+    using F = FftShape<N1, E>;
+    static constexpr int NT = 64 * W;                                // threads
     static constexpr int COLS = (F::B < N2) ? F::B : N2;             // per wave
-    static constexpr int GA = (SMOL_WAVES * COLS < N2) ? SMOL_WAVES * COLS : N2;  // per unit
+    static constexpr int GA = (W * COLS < N2) ? W * COLS : N2;       // per unit
     static constexpr int WUSED = GA / COLS;
     static constexpr int NG = N2 / GA;                                // column groups
-    static constexpr int LDS = SMOL_WAVES * 64 * F::E;                // entries
+    static constexpr int LDS = W * 64 * F::E;                         // entries
     static __host__ __device__ int units(int R) { return R * NG; }
     static __host__ __device__ int red_jobs() { return NG; }
 
     // one unit = (rank al, group of GA columns); whole workgroup
     __device__ static void run(const RhsPlanDev &P, const Pro &in, int unit, C *lds)
     {
-        __shared__ double sh[SMOL_WAVES * 4];
+        __shared__ double sh[W * 4];
         const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
         const int f = lane / F::G, g = lane % F::G;
         const int al = unit / NG, grp = unit % NG;
@@ -151,7 +154,7 @@ struct PhaseA {
         const bool active = (w < WUSED) && (f < COLS);
         const int64_t M = P.M;
         const double *Ua = P.U + (int64_t)al * P.ustride, *Va = P.V + (int64_t)al * P.ustride;
-        FftTw<N1, false, C> tw;
+        FftTw<N1, false, C, E> tw;
         C t4[F::E];
         if (active) {
             tw.load(g, P.rt);
@@ -211,7 +214,7 @@ struct PhaseA {
         __syncthreads();
         // store rows of GA consecutive columns
         C *Za = (C *)P.Z + ((int64_t)al << P.logL) + grp * GA;
-        for (int e = tid; e < GA * N1; e += SMOL_WG) {
+        for (int e = tid; e < GA * N1; e += NT) {
             const int c = e % GA, k1 = e / GA;
             Za[(int64_t)k1 * N2 + c] = lds[(c / COLS) * 64 * F::E + (c % COLS) * N1 + k1];
         }
@@ -227,7 +230,7 @@ struct PhaseA {
                 sh[w * 4 + 3] = sp;
             }
             __syncthreads();
-            if (tid < 4) P.red_part[((int64_t)grp * P.R + al) * 4 + tid] = sum_waves(sh, 4, tid);
+            if (tid < 4) P.red_part[((int64_t)grp * P.R + al) * 4 + tid] = sum_waves<W>(sh, 4, tid);
         }
     }
 };
@@ -236,10 +239,12 @@ struct PhaseA {
 // Phase B
 // --------------------------------------------------------------------------
 
-template <int N1, int N2, class C>
+// E: elements per lane of the row transforms; W: waves per workgroup.
+template <int N1, int N2, class C, int E = fft_default_e(N2), int W = SMOL_WAVES>
 struct PhaseB {
-    using F = FftShape<N2>;
-    static constexpr int SLOTS = SMOL_WAVES * F::B;  // row transforms per round
+    using F = FftShape<N2, E>;
+    static constexpr int NT = 64 * W;
+    static constexpr int SLOTS = W * F::B;           // row transforms per round
     static constexpr int AL_PER_ROUND = SLOTS / 2;   // ranks per round (2 rows each)
     static __host__ __device__ int units() { return N1 / 2 + 1; }
     // LDS entries: SLOTS rows + P for the two rows
@@ -255,9 +260,9 @@ struct PhaseB {
         const bool single = (k1 == k1p);  // k1 = 0 or N1/2
         C *rows = lds;
         C *P1 = lds + SLOTS * N2, *P2 = P1 + N2;
-        FftTw<N2, false, C> twf;
+        FftTw<N2, false, C, E> twf;
         twf.load(g, P.rt);
-        for (int k2 = tid; k2 < N2; k2 += SMOL_WG) P1[k2] = czero<C>();
+        for (int k2 = tid; k2 < N2; k2 += NT) P1[k2] = czero<C>();
         for (int a0 = 0; a0 < P.R; a0 += AL_PER_ROUND) {
             const int na = min(AL_PER_ROUND, P.R - a0);
             // slot 2m holds rank a0+m row k1, slot 2m+1 its row N1-k1
@@ -276,7 +281,7 @@ struct PhaseB {
                 }
             }
             __syncthreads();
-            for (int k2 = tid; k2 < N2; k2 += SMOL_WG) {
+            for (int k2 = tid; k2 < N2; k2 += NT) {
                 // partner of (k1, k2) is (k1p, k2p)
                 const int k2p = (k1 == 0) ? ((N2 - k2) & (N2 - 1)) : (N2 - 1 - k2);
                 C acc = P1[k2];
@@ -290,7 +295,7 @@ struct PhaseB {
             __syncthreads();
         }
         // divide by 4i: x / (4i) = (x.y, -x.x) / 4; partner row by conjugate reversal
-        for (int k2 = tid; k2 < N2; k2 += SMOL_WG) {
+        for (int k2 = tid; k2 < N2; k2 += NT) {
             const C q = div4i(P1[k2]);
             P1[k2] = q;
             if (!single) P2[N2 - 1 - k2] = cconj(q);
@@ -299,7 +304,7 @@ struct PhaseB {
         // inverse DFT over k2 of rows k1 (slot 0) and N1-k1 (slot 1)
         if (slot < (single ? 1 : 2)) {
             const int krow = slot ? k1p : k1;
-            FftTw<N2, true, C> twi;
+            FftTw<N2, true, C, E> twi;
             twi.load(g, P.rt);
             C t4[F::E];
             step_twiddles<F::E, true>(P.rt, P.logL, (uint32_t)krow, g, F::G, t4);
@@ -321,10 +326,11 @@ struct PhaseB {
 
 // Sum reduction partials [njobs][R][4] in a fixed order into red[R][4]
 // (threads take fixed stripes of jobs, then the stripes are added in order).
+template <int NT = SMOL_WG>
 __device__ inline void finalize_reductions(const RhsPlanDev &P, int njobs)
 {
-    __shared__ double sh[SMOL_WG];
-    const int tid = threadIdx.x, nq = 4 * P.R, ns = SMOL_WG / nq;
+    __shared__ double sh[NT];
+    const int tid = threadIdx.x, nq = 4 * P.R, ns = NT / nq;
     const int q = tid % nq, s = tid / nq;
     double acc = 0.0;
     if (s < ns)
@@ -342,18 +348,21 @@ __device__ inline void finalize_reductions(const RhsPlanDev &P, int njobs)
 // Phase C
 // --------------------------------------------------------------------------
 
-template <int N1, int N2, class C>
+// E: elements per lane of the column transforms (inverse, and the fused
+// next column pass); W: waves per workgroup.
+template <int N1, int N2, class C, int E = fft_default_e(N1), int W = SMOL_WAVES>
 struct PhaseC {
-    using F = FftShape<N1>;
+    using F = FftShape<N1, E>;
+    static constexpr int NT = 64 * W;
     static constexpr int HALF = N2 / 2;
     static constexpr int COLS = (F::B < HALF) ? F::B : HALF;  // packed columns per unit
     static constexpr int NPOS = COLS * N1;                     // outputs per unit
-    static constexpr int PP = (NPOS + SMOL_WG - 1) / SMOL_WG;  // per thread
+    static constexpr int PP = (NPOS + NT - 1) / NT;            // per thread
     static constexpr int LDS = 64 * F::E;                      // wave 0 scratch
-    // fused with the next column pass: four waves of scratch + the next
-    // stage state of the unit's 2 COLS columns (doubles)
+    // fused with the next column pass: W waves of scratch + the next stage
+    // state of the unit's 2 COLS columns (doubles)
     // (2 COLS columns x N1/2 rows of doubles = COLS N1 / 2 sixteen-byte entries)
-    static constexpr int LDS_FUSE = SMOL_WAVES * 64 * F::E + COLS * N1 / 2;
+    static constexpr int LDS_FUSE = W * 64 * F::E + COLS * N1 / 2;
     static __host__ __device__ int units() { return HALF / COLS; }
     static __host__ __device__ int jobs() { return units(); }
 
@@ -367,7 +376,7 @@ struct PhaseC {
     template <bool FUSE = false>
     __device__ static void run(const RhsPlanDev &P, const Epi &ep, int unit, C *lds)
     {
-        __shared__ double sh[SMOL_WAVES * 16];
+        __shared__ double sh[W * 16];
         const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
         const int64_t M = P.M;
         const int R = P.R;
@@ -382,7 +391,7 @@ struct PhaseC {
         double yv[PP], nv[PP], kv[PP][KMAX], Uv[PP][RPRE], Vv[PP][RPRE];
 #pragma unroll
         for (int j = 0; j < PP; ++j) {
-            const int e = tid + j * SMOL_WG;
+            const int e = tid + j * NT;
             qv[j] = -1;
             sz[j] = 0;
             yv[j] = nv[j] = 0.0;
@@ -412,7 +421,7 @@ struct PhaseC {
         if (w == 0) {
             const int f = lane / F::G, g = lane % F::G;
             const int ac = unit * COLS + f;
-            FftTw<N1, true, C> tw;
+            FftTw<N1, true, C, E> tw;
             tw.load(g, P.rt);
             C v[F::E];
             const C *Qp = (const C *)P.Qp;
@@ -437,7 +446,7 @@ struct PhaseC {
         for (int j = 0; j < PP; ++j) {
             yn[j] = 0.0;
             if (qv[j] >= 0) {
-                const int e = tid + j * SMOL_WG;
+                const int e = tid + j * NT;
                 const int b = e % (N1 / 2), hh = (e / (N1 / 2)) & 1, f = e / N1;
                 const C val = lds[f * (N1 / 2) + b];
                 const double c = (hh ? im_d(val) : re_d(val)) * invL;
@@ -472,13 +481,13 @@ struct PhaseC {
             for (int k = 0; k < KMAX; ++k) k1v[k] = (k < nk && ep.coef[k] != 0.0) ? ep.ks[k][0] : 0.0;
             yn1 = finish(ep, 0, 1.0, S1, y1, need_n ? ep.n[0] : 0.0, k1v, nk, acc);
         }
-        double *ycol = (double *)(lds + SMOL_WAVES * 64 * F::E);
+        double *ycol = (double *)(lds + W * 64 * F::E);
         if constexpr (FUSE) {
             // next stage state by (local column, row) for the column pass below
 #pragma unroll
             for (int j = 0; j < PP; ++j) {
                 if (qv[j] >= 0) {
-                    const int e = tid + j * SMOL_WG;
+                    const int e = tid + j * NT;
                     const int b = e % (N1 / 2), hh = (e / (N1 / 2)) & 1, f = e / N1;
                     const int wrap = (unit * COLS + f + 1 + hh * HALF) == N2;
                     const int n1 = b + wrap;
@@ -529,7 +538,7 @@ struct PhaseC {
                     for (int k = 0; k < 4 * na; ++k) sh[w * 16 + k] = s4[k];
                 __syncthreads();
                 if (tid < 4 * na)
-                    P.red_part[((int64_t)unit * R + a0) * 4 + tid] = sum_waves(sh, 16, tid);
+                    P.red_part[((int64_t)unit * R + a0) * 4 + tid] = sum_waves<W>(sh, 16, tid);
                 __syncthreads();
             }
         } else if (mode != C_RHS) {
@@ -540,7 +549,7 @@ struct PhaseC {
                 for (int q = 0; q < SMOL_EPART; ++q) sh[w * SMOL_EPART + q] = acc[q];
             __syncthreads();
             if (tid < SMOL_EPART)
-                ep.epart[(int64_t)unit * SMOL_EPART + tid] = sum_waves(sh, SMOL_EPART, tid);
+                ep.epart[(int64_t)unit * SMOL_EPART + tid] = sum_waves<W>(sh, SMOL_EPART, tid);
         }
         if constexpr (FUSE) {
             __syncthreads();
@@ -555,10 +564,10 @@ struct PhaseC {
         const int lane = lane_id(), w = wave_id();
         const int f = lane / F::G, g = lane % F::G;
         const int64_t M = P.M;
-        FftTw<N1, false, C> tw;
+        FftTw<N1, false, C, E> tw;
         tw.load(g, P.rt);
         const int nj = 2 * COLS * P.R;
-        for (int r0 = 0; r0 < nj; r0 += SMOL_WAVES * F::B) {
+        for (int r0 = 0; r0 < nj; r0 += W * F::B) {
             const int job = r0 + w * F::B + f;
             if (job < nj) {
                 const int jj = job % (2 * COLS), al = job / (2 * COLS);

@@ -1,6 +1,7 @@
 // libsmol: C ABI, plans and kernel launches (gfx950).
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -9,51 +10,17 @@
 #include <tuple>
 #include <vector>
 
-#include "host.h"
+#include "sched.h"
+#include "schedule_table.h"
 
 SMOL_HIDDEN std::mutex g_mu;
 
 #define SMOL_VERSION "0.1.0"
 
 // --------------------------------------------------------------------------
-// Kernels (multi-launch form of the three phases)
+// Kernels of this unit: layout conversion, starting step, controller.  The
+// right-hand-side phase kernels live in phases_a/b/c.hip (see sched.h).
 // --------------------------------------------------------------------------
-
-// Map workgroup b to a logical index so that consecutive logical indices land
-// on the same XCD (workgroups are dealt round-robin over the 8 XCDs).
-__device__ __forceinline__ int xcd_remap(int b, int nb)
-{
-    if (nb % 8) return b;
-    return (b % 8) * (nb / 8) + b / 8;
-}
-
-template <int N1, int N2, class T>
-__global__ __launch_bounds__(SMOL_WG) void k_phaseA(RhsPlanDev P, Pro in, int nunits)
-{
-    extern __shared__ cd lds[];
-    const int unit = xcd_remap(blockIdx.x, gridDim.x);
-    if (unit < nunits) PhaseA<N1, N2, T>::run(P, in, unit, (T *)lds);
-}
-
-template <int N1, int N2, class T>
-__global__ __launch_bounds__(SMOL_WG) void k_phaseB(RhsPlanDev P, int red_jobs)
-{
-    extern __shared__ cd lds[];
-    const int u = blockIdx.x;
-    if (u == PhaseB<N1, N2, T>::units()) {
-        if (red_jobs > 0) finalize_reductions(P, red_jobs);
-        return;
-    }
-    PhaseB<N1, N2, T>::run(P, u, (T *)lds);
-}
-
-template <int N1, int N2, class T>
-__global__ __launch_bounds__(SMOL_WG) void k_phaseC(RhsPlanDev P, Epi ep, int nunits)
-{
-    extern __shared__ cd lds[];
-    const int unit = xcd_remap(blockIdx.x, gridDim.x);
-    if (unit < nunits) PhaseC<N1, N2, T>::template run<false>(P, ep, unit, (T *)lds);
-}
 
 // Layout conversion of `rows` vectors of M sizes: natural <-> transposed.
 __global__ void k_to_tr(const double *src, double *dst, int64_t M, int rows, int64_t sstride,
@@ -72,52 +39,6 @@ __global__ void k_from_tr(const double *src, double *dst, int64_t M, int logL)
         dst[i] = src[pos_tr(i, logL)];
 }
 
-
-// --------------------------------------------------------------------------
-// Integration kernels: the same phases, buffers chosen from the control block
-// --------------------------------------------------------------------------
-
-template <int N1, int N2, class T>
-__global__ __launch_bounds__(SMOL_WG) void k_int_A(IntegDev I, int stage, int nunits)
-{
-    const IntegCtl &c = *I.ctl;
-    if (c.done) return;
-    extern __shared__ cd lds[];
-    const Tableau &tab = c_tab[c.method];
-    const RhsPlanDev P = plan_of(I, c);
-    const Pro in = stage_pro(I, c, tab, stage);
-    const int unit = xcd_remap(blockIdx.x, gridDim.x);
-    if (unit < nunits) PhaseA<N1, N2, T>::run(P, in, unit, (T *)lds);
-}
-
-template <int N1, int N2, class T>
-__global__ __launch_bounds__(SMOL_WG) void k_int_B(IntegDev I, int stage)
-{
-    const IntegCtl &c = *I.ctl;
-    if (c.done) return;
-    extern __shared__ cd lds[];
-    const RhsPlanDev P = plan_of(I, c);
-    const int u = blockIdx.x;
-    if (u == PhaseB<N1, N2, T>::units()) {
-        // partials of y come from phase A (stages 0..2) or the previous finish
-        finalize_reductions(P, stage <= 2 ? PhaseA<N1, N2, T>::red_jobs() : PhaseC<N1, N2, T>::units());
-        return;
-    }
-    PhaseB<N1, N2, T>::run(P, u, (T *)lds);
-}
-
-template <int N1, int N2, class T, bool FUSE>
-__global__ __launch_bounds__(SMOL_WG) void k_int_C(IntegDev I, int stage, int nunits)
-{
-    const IntegCtl &c = *I.ctl;
-    if (c.done) return;
-    extern __shared__ cd lds[];
-    const Tableau &tab = c_tab[c.method];
-    const RhsPlanDev P = plan_of(I, c);
-    const Epi ep = stage_epi(I, c, tab, stage);
-    const int unit = xcd_remap(blockIdx.x, gridDim.x);
-    if (unit < nunits) PhaseC<N1, N2, T>::template run<FUSE>(P, ep, unit, (T *)lds);
-}
 
 __global__ __launch_bounds__(SMOL_WG) void k_init_h0(IntegDev I, int njobs) { init_h0_step(I, njobs); }
 __global__ __launch_bounds__(SMOL_WG) void k_init_h(IntegDev I, int njobs) { init_h_step(I, njobs); }
@@ -146,7 +67,26 @@ struct Plan {
     IntegCtl *host = nullptr;      // pinned mirror
     hipStream_t cap = nullptr;     // capture stream
     hipGraphExec_t graph[2] = {nullptr, nullptr};
+    // launch schedule: variant of kernels A, B, C and their grids
+    int var[3] = {0, 0, 0};
+    PhaseDims dA{}, dB{}, dC{}, dCf{};
 };
+
+// Schedule variants per transform length for FP64 plans (float-float plans
+// use variant 0), initialised from the tuned table and changed by
+// smol_set_schedule / smol_autotune.
+int g_sched[SMOL_LOG_LMAX + 1][3];
+bool g_sched_init = false;
+
+void sched_init()
+{
+    if (g_sched_init) return;
+    memset(g_sched, 0, sizeof(g_sched));
+    for (const auto &row : k_sched_table)
+        if (row[0] >= 0 && row[0] <= SMOL_LOG_LMAX)
+            for (int k = 0; k < 3; ++k) g_sched[row[0]][k] = row[1 + k];
+    g_sched_init = true;
+}
 
 std::map<int, DevRoots> g_roots;
 std::map<std::tuple<int, int64_t, int, int>, Plan *> g_plans;
@@ -179,6 +119,27 @@ SMOL_HIDDEN int get_roots(int dev, DevRoots **out)
 }
 
 namespace {
+
+// Point plan p at schedule v[3] (grids, LDS); drops captured graphs.
+int set_plan_sched(Plan *p, const int *v)
+{
+    PhaseDims a, b, c, cf;
+    int rc;
+    if ((rc = phase_dims(p->logL, p->precision, PH_A, v[0], p->R, false, &a))) return rc;
+    if ((rc = phase_dims(p->logL, p->precision, PH_B, v[1], p->R, false, &b))) return rc;
+    if ((rc = phase_dims(p->logL, p->precision, PH_C, v[2], p->R, false, &c))) return rc;
+    if ((rc = phase_dims(p->logL, p->precision, PH_C, v[2], p->R, true, &cf))) return rc;
+    for (auto &g : p->graph) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+    for (int k = 0; k < 3; ++k) p->var[k] = v[k];
+    p->dA = a;
+    p->dB = b;
+    p->dC = c;
+    p->dCf = cf;
+    return SMOL_OK;
+}
 
 void free_plan(Plan *p)
 {
@@ -232,6 +193,13 @@ int get_plan(int64_t M, int R, int precision, Plan **out)
     }
     p->red = p->red_part + (size_t)N2 * R * 4;
     p->epart = p->red + (size_t)R * 4;
+    sched_init();
+    static const int v0[3] = {0, 0, 0};
+    int rc = set_plan_sched(p, precision == SMOL_FP64 ? g_sched[logL] : v0);
+    if (rc) {
+        free_plan(p);
+        return rc;
+    }
     g_plans[key] = p;
     *out = p;
     return SMOL_OK;
@@ -260,68 +228,32 @@ RhsPlanDev dev_plan(const Plan *p, const DevRoots *r, const double *U, const dou
 }
 
 // Launch phases A, B, C for one right-hand side.
-template <int N1, int N2, class T>
-int launch_rhs_t(const RhsPlanDev &P, const Pro &in, const Epi &ep, hipStream_t s)
+int launch_rhs(const Plan *p, const RhsPlanDev &P, const Pro &in, const Epi &ep, hipStream_t s)
 {
-    using A = PhaseA<N1, N2, T>;
-    using B = PhaseB<N1, N2, T>;
-    using C = PhaseC<N1, N2, T>;
-    const int nA = A::units(P.R), nC = C::units();
-    hipLaunchKernelGGL((k_phaseA<N1, N2, T>), dim3(nA), dim3(SMOL_WG), sizeof(cd) * A::LDS, s, P,
-                       in, nA);
-    const int redj = (in.mode == A_COMBINE) ? A::red_jobs() : 0;
-    hipLaunchKernelGGL((k_phaseB<N1, N2, T>), dim3(B::units() + 1), dim3(SMOL_WG),
-                       sizeof(cd) * B::LDS, s, P, redj);
-    hipLaunchKernelGGL((k_phaseC<N1, N2, T>), dim3(nC), dim3(SMOL_WG), sizeof(cd) * C::LDS, s, P,
-                       ep, nC);
+    int rc;
+    if ((rc = launch_rhs_A(p->logL, p->precision, p->var[0], P, in, s))) return rc;
+    const int redj = (in.mode == A_COMBINE) ? p->dA.jobs : 0;
+    if ((rc = launch_rhs_B(p->logL, p->precision, p->var[1], P, redj, s))) return rc;
+    if ((rc = launch_rhs_C(p->logL, p->precision, p->var[2], P, ep, s))) return rc;
     HIP_TRY(hipGetLastError());
     return SMOL_OK;
 }
-
-
-struct LaunchRhs {
-    template <int N1, int N2, class T>
-    static int run(const RhsPlanDev &P, const Pro &in, const Epi &ep, hipStream_t s)
-    {
-        return launch_rhs_t<N1, N2, T>(P, in, ep, s);
-    }
-};
 
 // One stage (or starting-step evaluation) of the integrator.  Stages 0..2
 // run A, B, C; from stage 3 on the column pass was done by the previous
 // stage's fused finish, so only B and C run; the finish of stages
 // 2..S-1 is fused with the next column pass.
-struct LaunchStage {
-    template <int N1, int N2, class T>
-    static int run(const IntegDev &I, int stage, int S, hipStream_t s)
-    {
-        using A = PhaseA<N1, N2, T>;
-        using B = PhaseB<N1, N2, T>;
-        using C = PhaseC<N1, N2, T>;
-        const int nA = A::units(I.R), nC = C::units();
-        if (stage <= 2)
-            hipLaunchKernelGGL((k_int_A<N1, N2, T>), dim3(nA), dim3(SMOL_WG), sizeof(cd) * A::LDS, s,
-                               I, stage, nA);
-        hipLaunchKernelGGL((k_int_B<N1, N2, T>), dim3(B::units() + 1), dim3(SMOL_WG),
-                           sizeof(cd) * B::LDS, s, I, stage);
-        if (stage >= 2 && stage < S)
-            hipLaunchKernelGGL((k_int_C<N1, N2, T, true>), dim3(nC), dim3(SMOL_WG),
-                               sizeof(cd) * C::LDS_FUSE, s, I, stage, nC);
-        else
-            hipLaunchKernelGGL((k_int_C<N1, N2, T, false>), dim3(nC), dim3(SMOL_WG),
-                               sizeof(cd) * C::LDS, s, I, stage, nC);
-        HIP_TRY(hipGetLastError());
-        return SMOL_OK;
-    }
-};
-
-struct PhaseCJobs {
-    template <int N1, int N2, class T>
-    static int run()
-    {
-        return PhaseC<N1, N2, T>::units();
-    }
-};
+int launch_stage(const Plan *p, const IntegDev &I, int stage, int S, hipStream_t s)
+{
+    int rc;
+    if (stage <= 2 && (rc = launch_int_A(p->logL, p->precision, p->var[0], I, stage, s))) return rc;
+    if ((rc = launch_int_B(p->logL, p->precision, p->var[1], I, stage, p->dA.jobs, p->dC.jobs, s)))
+        return rc;
+    const bool fuse = stage >= 2 && stage < S;
+    if ((rc = launch_int_C(p->logL, p->precision, p->var[2], fuse, I, stage, s))) return rc;
+    HIP_TRY(hipGetLastError());
+    return SMOL_OK;
+}
 
 int alloc_integ(Plan *p)
 {
@@ -373,10 +305,9 @@ int get_step_graph(Plan *p, const IntegDev &I, int method, hipGraphExec_t *out)
     hipGraph_t g;
     HIP_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
     int rc = SMOL_OK;
-    const int nC = with_shape<PhaseCJobs>(p->logL, SMOL_FP64);
+    const int nC = p->dC.jobs;
     for (int a = 0; a < SMOL_GRAPH_ATTEMPTS; ++a) {
-        for (int st = 2; st <= S && rc == SMOL_OK; ++st)
-            rc = with_shape<LaunchStage>(p->logL, p->precision, I, st, S, p->cap);
+        for (int st = 2; st <= S && rc == SMOL_OK; ++st) rc = launch_stage(p, I, st, S, p->cap);
         hipLaunchKernelGGL(k_ctrl, dim3(1), dim3(SMOL_WG), 0, p->cap, I, nC);
     }
     hipError_t e = hipStreamEndCapture(p->cap, &g);
@@ -435,7 +366,7 @@ extern "C" int smol_rhs(int64_t M, int32_t R, const double *U, const double *V, 
     ep.mode = C_RHS;
     ep.y = n;
     ep.out = dndt;
-    return with_shape<LaunchRhs>(p->logL, precision, P, in, ep, (hipStream_t)stream);
+    return launch_rhs(p, P, in, ep, (hipStream_t)stream);
 }
 
 extern "C" int smol_release_plans(void)
@@ -541,12 +472,12 @@ extern "C" int smol_integrate_ex(int64_t M, int32_t R, const double *U, const do
     hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, U, I.Ut, M, R, M, I.Mt, p->logL);
     hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, V, I.Vt, M, R, M, I.Mt, p->logL);
     hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, n0, I.nb[0], M, 1, M, I.Mt, p->logL);
-    const int nC = with_shape<PhaseCJobs>(p->logL, SMOL_FP64);
+    const int nC = p->dC.jobs;
     // starting step: S(n0), h0, S(n0 + h0 f0), h
-    if ((rc = with_shape<LaunchStage>(p->logL, p->precision, I, 0, 0, s))) return rc;
+    if ((rc = launch_stage(p, I, 0, 0, s))) return rc;
     hipLaunchKernelGGL(k_init_h0, dim3(1), dim3(SMOL_WG), 0, s, I, nC);
     if (!(o.h0 > 0)) {
-        if ((rc = with_shape<LaunchStage>(p->logL, p->precision, I, 1, 0, s))) return rc;
+        if ((rc = launch_stage(p, I, 1, 0, s))) return rc;
         hipLaunchKernelGGL(k_init_h, dim3(1), dim3(SMOL_WG), 0, s, I, nC);
     }
     HIP_TRY(hipGetLastError());
@@ -583,45 +514,35 @@ extern "C" int smol_integrate(int64_t M, int32_t R, const double *U, const doubl
 
 
 namespace {
-struct ProfileRhs {
-    template <int N1, int N2, class T>
-    static int run(const RhsPlanDev &P, const Pro &in, const Epi &ep, int iters, float *ms,
-                   hipStream_t s)
-    {
-        using A = PhaseA<N1, N2, T>;
-        using B = PhaseB<N1, N2, T>;
-        using C = PhaseC<N1, N2, T>;
-        const int nA = A::units(P.R), nC = C::units();
-        hipEvent_t ev[5];
-        for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
-        HIP_TRY(hipEventRecord(ev[0], s));
-        for (int i = 0; i < iters; ++i)
-            hipLaunchKernelGGL((k_phaseA<N1, N2, T>), dim3(nA), dim3(SMOL_WG), sizeof(cd) * A::LDS, s,
-                               P, in, nA);
-        HIP_TRY(hipEventRecord(ev[1], s));
-        for (int i = 0; i < iters; ++i)
-            hipLaunchKernelGGL((k_phaseB<N1, N2, T>), dim3(B::units() + 1), dim3(SMOL_WG),
-                               sizeof(cd) * B::LDS, s, P, A::red_jobs());
-        HIP_TRY(hipEventRecord(ev[2], s));
-        for (int i = 0; i < iters; ++i)
-            hipLaunchKernelGGL((k_phaseC<N1, N2, T>), dim3(nC), dim3(SMOL_WG), sizeof(cd) * C::LDS, s,
-                               P, ep, nC);
-        HIP_TRY(hipEventRecord(ev[3], s));
-        for (int i = 0; i < iters; ++i) {
-            int rc = launch_rhs_t<N1, N2, T>(P, in, ep, s);
-            if (rc) return rc;
-        }
-        HIP_TRY(hipEventRecord(ev[4], s));
-        HIP_TRY(hipEventSynchronize(ev[4]));
-        for (int k = 0; k < 4; ++k) {
-            float t;
-            HIP_TRY(hipEventElapsedTime(&t, ev[k], ev[k + 1]));
-            ms[k] = t / (float)iters;
-        }
-        for (auto &e : ev) HIP_TRY(hipEventDestroy(e));
-        return SMOL_OK;
+// Mean milliseconds per launch of each phase (iters back-to-back launches)
+// and per whole right-hand side, with HIP events on stream s.
+int profile_phases(const Plan *p, const RhsPlanDev &P, const Pro &in, const Epi &ep, int iters,
+                   float *ms, hipStream_t s)
+{
+    hipEvent_t ev[5];
+    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+    int rc = SMOL_OK;
+    HIP_TRY(hipEventRecord(ev[0], s));
+    for (int i = 0; i < iters && !rc; ++i) rc = launch_rhs_A(p->logL, p->precision, p->var[0], P, in, s);
+    HIP_TRY(hipEventRecord(ev[1], s));
+    for (int i = 0; i < iters && !rc; ++i)
+        rc = launch_rhs_B(p->logL, p->precision, p->var[1], P, p->dA.jobs, s);
+    HIP_TRY(hipEventRecord(ev[2], s));
+    for (int i = 0; i < iters && !rc; ++i) rc = launch_rhs_C(p->logL, p->precision, p->var[2], P, ep, s);
+    HIP_TRY(hipEventRecord(ev[3], s));
+    for (int i = 0; i < iters && !rc; ++i) rc = launch_rhs(p, P, in, ep, s);
+    HIP_TRY(hipEventRecord(ev[4], s));
+    HIP_TRY(hipEventSynchronize(ev[4]));
+    if (rc) return rc;
+    HIP_TRY(hipGetLastError());
+    for (int k = 0; k < 4; ++k) {
+        float t;
+        HIP_TRY(hipEventElapsedTime(&t, ev[k], ev[k + 1]));
+        ms[k] = t / (float)iters;
     }
-};
+    for (auto &e : ev) HIP_TRY(hipEventDestroy(e));
+    return SMOL_OK;
+}
 }  // namespace
 
 // Times the kernels the integrator runs: vectors in the transposed layout.
@@ -651,7 +572,7 @@ extern "C" int smol_profile_rhs(int64_t M, int32_t R, const double *U, const dou
     ep.mode = C_RHS;
     ep.y = I.nb[0];
     ep.out = I.kslot[0];
-    rc = with_shape<ProfileRhs>(p->logL, SMOL_FP64, P, in, ep, iters, ms_out, s);
+    rc = profile_phases(p, P, in, ep, iters, ms_out, s);
     if (rc) return rc;
     hipLaunchKernelGGL(k_from_tr, dim3(256), dim3(256), 0, s, I.kslot[0], dndt, M, p->logL);
     HIP_TRY(hipGetLastError());
@@ -659,3 +580,117 @@ extern "C" int smol_profile_rhs(int64_t M, int32_t R, const double *U, const dou
     return SMOL_OK;
 }
 
+
+// --------------------------------------------------------------------------
+// Launch schedules and the autotuner
+// --------------------------------------------------------------------------
+
+namespace {
+bool sched_valid(int logL, const int32_t *v)
+{
+    PhaseDims d;
+    for (int ph = 0; ph < 3; ++ph)
+        if (v[ph] < 0 || v[ph] >= SMOL_NVAR || phase_dims(logL, SMOL_FP64, ph, v[ph], 1, false, &d))
+            return false;
+    return true;
+}
+
+int set_schedule_locked(int logL, const int32_t *v)
+{
+    sched_init();
+    if (logL < 6 || logL > SMOL_LOG_LMAX || !v || !sched_valid(logL, v)) return SMOL_EINVAL;
+    int w[3] = {v[0], v[1], v[2]};
+    for (auto &kv : g_plans) {
+        Plan *p = kv.second;
+        if (p->precision != SMOL_FP64 || p->logL != logL) continue;
+        if (p->var[0] == w[0] && p->var[1] == w[1] && p->var[2] == w[2]) continue;
+        int rc = set_plan_sched(p, w);
+        if (rc) return rc;
+    }
+    for (int k = 0; k < 3; ++k) g_sched[logL][k] = w[k];
+    return SMOL_OK;
+}
+}  // namespace
+
+extern "C" int smol_set_schedule(int32_t logL, const int32_t *variants)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    return set_schedule_locked(logL, variants);
+}
+
+extern "C" int smol_get_schedule(int32_t logL, int32_t *variants)
+{
+    if (logL < 6 || logL > SMOL_LOG_LMAX || !variants) return SMOL_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    sched_init();
+    for (int k = 0; k < 3; ++k) variants[k] = g_sched[logL][k];
+    return SMOL_OK;
+}
+
+extern "C" int smol_autotune(int64_t M, int32_t R, const double *U, const double *V, double lambda,
+                             const double *n0, int32_t method, int32_t attempts, int32_t reps,
+                             int32_t *variants_out, float *ms_out, void *stream)
+{
+    int rc = check_common(M, R, U, V, lambda);
+    if (rc) return rc;
+    if (!n0 || !variants_out || attempts < 1 || reps < 1) return SMOL_EINVAL;
+    if (method != SMOL_BS32 && method != SMOL_DP54) return SMOL_EINVAL;
+    const int logL = fft_log2(M);
+    double *scratch = nullptr;
+    HIP_TRY(hipMalloc(&scratch, sizeof(double) * (size_t)M));
+    smol_options o{};
+    o.max_steps = attempts;
+    // seconds per step attempt of schedule v: one untimed run (captures the
+    // step graph), then the best of `reps` timed runs of `attempts` attempts
+    auto time_of = [&](const int32_t *v, double *sec) -> int {
+        int r = smol_set_schedule(logL, v);
+        if (r) return r;
+        double best = 1e30;
+        for (int k = 0; k <= reps; ++k) {
+            smol_stats st;
+            auto t0 = std::chrono::steady_clock::now();
+            r = smol_integrate_ex(M, R, U, V, lambda, n0, 1e300, 1e-6, 1e-12, method, SMOL_FP64, &o,
+                                  scratch, &st, stream);
+            auto t1 = std::chrono::steady_clock::now();
+            if (r != SMOL_OK && r != SMOL_EMAXSTEPS) return r;
+            const double dt = std::chrono::duration<double>(t1 - t0).count();
+            if (k > 0 && dt < best) best = dt;
+        }
+        *sec = best / attempts;
+        return SMOL_OK;
+    };
+    int32_t cur[3];
+    smol_get_schedule(logL, cur);
+    double best = 0.0;
+    rc = time_of(cur, &best);
+    const double start = best;
+    // coordinate descent over the kernels, largest first; a change must gain 2 %
+    for (int ph : {PH_C, PH_B, PH_A}) {
+        if (rc || logL < SMOL_TUNE_MIN_LOGL) break;
+        for (int v = 0; v < SMOL_NVAR && !rc; ++v) {
+            int32_t cand[3] = {cur[0], cur[1], cur[2]};
+            if (v == cur[ph]) continue;
+            cand[ph] = v;
+            {
+                std::lock_guard<std::mutex> lk(g_mu);
+                if (!sched_valid(logL, cand)) continue;
+            }
+            double t;
+            rc = time_of(cand, &t);
+            if (!rc && t < 0.98 * best) {
+                best = t;
+                for (int k = 0; k < 3; ++k) cur[k] = cand[k];
+            }
+        }
+    }
+    int rc2 = smol_set_schedule(logL, cur);
+    (void)hipFree(scratch);
+    if (rc) return rc;
+    if (rc2) return rc2;
+    for (int k = 0; k < 3; ++k) variants_out[k] = cur[k];
+    if (ms_out) {
+        ms_out[0] = (float)(start * 1e3);
+        ms_out[1] = (float)(best * 1e3);
+    }
+    return SMOL_OK;
+}

@@ -58,3 +58,37 @@ def test_no_fallback_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(smol, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError):
         smol.lib()
+
+
+def test_schedule_variants_host_logic(lib):
+    """Which kernel variants exist per transform length (host-side table, no
+    device work): variant 0 everywhere; variants 1..3 only for L >= 2^12,
+    the radix-4 variants (2, 3) only for transforms of length <= 256, and
+    no variant whose LDS exceeds a workgroup's share (the 8-wave row-pair
+    pass at L = 2^20)."""
+    import paper_2407_16559_amd as smol
+    saved = {L: smol.get_schedule(L) for L in range(6, 21)}
+    try:
+        for logL in range(6, 21):
+            N1, N2 = 2 ** ((logL + 1) // 2), 2 ** (logL // 2)
+            for ph, N in ((0, N1), (1, N2), (2, N1)):
+                for v in range(4):
+                    want = [0, 0, 0]
+                    want[ph] = v
+                    ok = v == 0 or (logL >= 12 and (v < 2 or N <= 256))
+                    ok = ok and not (logL == 20 and ph == 1 and v == 1)
+                    if ok:
+                        smol.set_schedule(logL, want)
+                        assert smol.get_schedule(logL) == tuple(want)
+                    else:
+                        with pytest.raises(smol.SmolError):
+                            smol.set_schedule(logL, want)
+        for bad in ((4, 0, 0), (-1, 0, 0)):
+            with pytest.raises(smol.SmolError):
+                smol.set_schedule(16, bad)
+        for logL in (5, 21):
+            with pytest.raises(smol.SmolError):
+                smol.get_schedule(logL)
+    finally:
+        for L, v in saved.items():
+            smol.set_schedule(L, v)

@@ -140,3 +140,23 @@ def batch_draws(n_inst=256, seed=0, m_lo_log2=12, m_hi_log2=17):
 def batch_instance(d):
     U, V = brownian_rank3(d["M"], d["a"])
     return U, V, d["lam"], exponential_start(d["M"], d["s0"])
+
+
+# Layer shapes (fan_in, fan_out) of the step proposer network; the flat
+# parameter vector holds each layer's weights (fan_out x fan_in, row-major)
+# followed by its biases.
+MLP_LAYERS = ((9, 64), (64, 64), (64, 1))
+
+
+def mlp_init(seed):
+    """Initial proposer parameters: weights uniform in +-sqrt(6/(fan_in+fan_out))
+    (Glorot and Bengio 2010) from SplitMix64 draws, biases zero."""
+    g = SplitMix64(seed)
+    n = sum(i * o + o for i, o in MLP_LAYERS)
+    p = np.zeros(n)
+    off = 0
+    for fan_in, fan_out in MLP_LAYERS:
+        lim = math.sqrt(6.0 / (fan_in + fan_out))
+        p[off:off + fan_in * fan_out] = lim * (2.0 * g.uniforms(fan_in * fan_out) - 1.0)
+        off += fan_in * fan_out + fan_out
+    return p
