@@ -22,6 +22,38 @@ sys.path.insert(0, ROOT)
 # MI355X published peak HBM3E bandwidth (bytes/s)
 HBM_PEAK = 8.0e12
 
+# sources of the right-hand-side kernels; hardware byte counts recorded in
+# profiles/ are used only while these files are unchanged
+KERNEL_SOURCES = ["common.h", "ff.h", "fft.h", "rhs.h", "kernels.h", "sched.h",
+                  "schedule_table.h", "phases_a.hip", "phases_b.hip", "phases_c.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_rhs_M65536_R3.md")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2407_16559_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by a copy of known size), or None
+    if the summary is missing or the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    import re
+    m = re.search(r"source hash: `([0-9a-f]+)`", text)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    m = re.search(r"^\| " + kernel + r" \|[^\n]*\| (\d+) \|\s*$", text, re.M)
+    return int(m.group(1)) if m else None
+
 
 def rhs_bytes(M, R, L):
     """Algorithmic HBM bytes of the three right-hand-side kernels (FP64):
@@ -43,10 +75,20 @@ def cpu_baseline(U, V, lam, n0, per_step_rhs):
     t0 = time.perf_counter()
     oracle.rhs(U, V, lam, n0, threads=threads)
     dt = time.perf_counter() - t0
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": 1.0 / (per_step_rhs * dt), "unit": "accepted steps/s", "cores": threads,
             "kind": "oracle",
             "sample": f"one direct O(M^2 R) right-hand side at M={n0.size} "
-                      f"({dt:.2f} s), times {per_step_rhs} per DP5 step"}
+                      f"({dt:.2f} s on {threads} threads of {os.cpu_count()} x {model}), "
+                      f"times {per_step_rhs} per DP5 step"}
 
 
 def main():
@@ -56,9 +98,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--t-end", type=float, default=None, help="shorter runs (profiling)")
-    ap.add_argument("--workload", choices=["single", "batch", "learned"], default="single",
+    ap.add_argument("--workload", choices=["single", "batch", "learned", "kernels"],
+                    default="single",
                     help="single: the M=65536 DP5 instance (default); batch: the 256-instance "
-                         "sweep; learned: train the step proposer, then learned vs PI at M=262144")
+                         "sweep; learned: train the step proposer, then learned vs PI at "
+                         "M=262144; kernels: --steps launches of each RHS kernel plus a 64 MiB "
+                         "device copy (for hardware-counter runs)")
     ap.add_argument("--no-accuracy-check", action="store_true",
                     help="skip the tight reference run that selects rtol (profiling)")
     ap.add_argument("--train-instances", type=int, default=128)
@@ -80,6 +125,8 @@ def main():
         return bench_batch(args, smol, W, torch, dev)
     if args.workload == "learned":
         return bench_learned(args, smol, W, torch, dev)
+    if args.workload == "kernels":
+        return bench_kernels(args, smol, W, torch, dev)
     c = W.CONFIGS[2]
     t_end = args.t_end if args.t_end else c["t_end"]
     U, V, lam, n0 = W.config_instance(2)
@@ -128,7 +175,8 @@ def main():
     dom = max(("phase_a", "phase_b", "phase_c"), key=lambda k: prof[k])
     achieved = nbytes[dom] / (prof[dom] * 1e-3)
     roof = {"bound": "hbm", "kernel": dom, "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": recorded_traffic(dom),
+            "alg_bytes": nbytes[dom],
             "ms_per_launch": {k: prof[k] for k in ("phase_a", "phase_b", "phase_c")},
             "rhs_ms": prof["rhs"],
             "rhs_alg_bytes": nbytes["rhs"],
@@ -214,6 +262,30 @@ def bench_batch(args, smol, W, torch, dev):
         "all_ok": all(s["status"] == 0 for s in stats),
     }
     print(json.dumps(line), flush=True)
+
+
+def bench_kernels(args, smol, W, torch, dev):
+    """The three right-hand-side kernels of the large instance (M = 65536,
+    at its start state), --steps launches of each and --steps whole RHS,
+    then --steps copies of a 64 MiB device buffer: the reference a hardware
+    byte counter is scaled by (each copy reads and writes 64 MiB)."""
+    import numpy as np
+    U, V, lam, n0 = W.config_instance(2)
+    M, R = U.shape[1], U.shape[0]
+    L = 1 << int(np.ceil(np.log2(2 * M - 2)))
+    Ud, Vd, nd = (torch.from_numpy(x).to(dev) for x in (U, V, W.exponential_start(M, 300.0)))
+    prof = smol.profile_rhs(Ud, Vd, lam, nd, iters=args.steps)
+    nbytes = 64 << 20
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": "kernels", "M": M, "R": R, "fft_length": L,
+                      "launches": args.steps, "ms_per_launch": prof,
+                      "alg_bytes": rhs_bytes(M, R, L), "copy_bytes_each_way": nbytes}),
+          flush=True)
 
 
 def bench_learned(args, smol, W, torch, dev):

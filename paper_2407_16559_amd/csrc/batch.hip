@@ -33,7 +33,7 @@ __global__ __launch_bounds__(SMOL_WG) void kb_A(BatchDev B, int stage)
     extern __shared__ cd lds[];
     const int b = B.owner[0][blockIdx.x];
     const IntegDev &I = B.inst[b];
-    const IntegCtl &c = *I.ctl;
+    const IntegCtl c = *I.ctl;  // one snapshot: all fields load together
     if (c.done) return;
     const RhsPlanDev P = plan_of(I, c);
     const Pro in = stage_pro(I, c, c_tab[c.method], stage);
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(SMOL_WG) void kb_B(BatchDev B, int stage)
     extern __shared__ cd lds[];
     const int b = B.owner[1][blockIdx.x];
     const IntegDev &I = B.inst[b];
-    const IntegCtl &c = *I.ctl;
+    const IntegCtl c = *I.ctl;  // one snapshot: all fields load together
     if (c.done) return;
     const RhsPlanDev P = plan_of(I, c);
     const int unit = blockIdx.x - B.first[1][b];
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(SMOL_WG) void kb_C(BatchDev B, int stage)
     extern __shared__ cd lds[];
     const int b = B.owner[2][blockIdx.x];
     const IntegDev &I = B.inst[b];
-    const IntegCtl &c = *I.ctl;
+    const IntegCtl c = *I.ctl;  // one snapshot: all fields load together
     if (c.done) return;
     const RhsPlanDev P = plan_of(I, c);
     const Epi ep = stage_epi(I, c, c_tab[c.method], stage);

@@ -6,11 +6,13 @@
 #include "sched.h"
 
 // Map workgroup b to a logical index so that consecutive logical indices land
-// on the same XCD (workgroups are dealt round-robin over the 8 XCDs).
+// on the same XCD (workgroups are dealt round-robin over the 8 XCDs, each with
+// its own L2): the first nb - nb % 8 workgroups are remapped, the rest kept.
 __device__ __forceinline__ int xcd_remap(int b, int nb)
 {
-    if (nb % 8) return b;
-    return (b % 8) * (nb / 8) + b / 8;
+    const int full = nb & ~7;
+    if (b >= full) return b;
+    return (b % 8) * (full / 8) + b / 8;
 }
 
 // ---- plain right-hand side -------------------------------------------------
@@ -27,7 +29,8 @@ template <int N1, int N2, class T, int E, int W>
 __global__ __launch_bounds__(64 * W) void k_phaseB(RhsPlanDev P, int red_jobs)
 {
     extern __shared__ cd lds[];
-    const int u = blockIdx.x;
+    // neighbouring row pairs share the cache lines of the column-major spectra
+    const int u = xcd_remap(blockIdx.x, gridDim.x);
     if (u == PhaseB<N1, N2, T, E, W>::units()) {
         if (red_jobs > 0) finalize_reductions<64 * W>(P, red_jobs);
         return;
@@ -48,7 +51,7 @@ __global__ __launch_bounds__(64 * W) void k_phaseC(RhsPlanDev P, Epi ep, int nun
 template <int N1, int N2, class T, int E, int W>
 __global__ __launch_bounds__(64 * W) void k_int_A(IntegDev I, int stage, int nunits)
 {
-    const IntegCtl &c = *I.ctl;
+    const IntegCtl c = *I.ctl;  // one snapshot: all fields load together
     if (c.done) return;
     extern __shared__ cd lds[];
     const Tableau &tab = c_tab[c.method];
@@ -63,11 +66,11 @@ __global__ __launch_bounds__(64 * W) void k_int_A(IntegDev I, int stage, int nun
 template <int N1, int N2, class T, int E, int W>
 __global__ __launch_bounds__(64 * W) void k_int_B(IntegDev I, int stage, int jobs_a, int jobs_c)
 {
-    const IntegCtl &c = *I.ctl;
+    const IntegCtl c = *I.ctl;  // one snapshot: all fields load together
     if (c.done) return;
     extern __shared__ cd lds[];
     const RhsPlanDev P = plan_of(I, c);
-    const int u = blockIdx.x;
+    const int u = xcd_remap(blockIdx.x, gridDim.x);
     if (u == PhaseB<N1, N2, T, E, W>::units()) {
         finalize_reductions<64 * W>(P, stage <= 2 ? jobs_a : jobs_c);
         return;
@@ -78,7 +81,7 @@ __global__ __launch_bounds__(64 * W) void k_int_B(IntegDev I, int stage, int job
 template <int N1, int N2, class T, int E, int W, bool FUSE>
 __global__ __launch_bounds__(64 * W) void k_int_C(IntegDev I, int stage, int nunits)
 {
-    const IntegCtl &c = *I.ctl;
+    const IntegCtl c = *I.ctl;  // one snapshot: all fields load together
     if (c.done) return;
     extern __shared__ cd lds[];
     const Tableau &tab = c_tab[c.method];

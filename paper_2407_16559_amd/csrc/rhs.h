@@ -163,19 +163,34 @@ struct PhaseA {
         C v[F::E];
         double sw = 0, st = 0, sr = 0, sp = 0;
         const bool comb = in.mode == A_COMBINE;
+        // every load first (the y store below could alias them, which would
+        // otherwise serialise one memory round trip per element)
+        constexpr int H = F::E / 2;
+        double y0[H], k0[H], u0[H], x0[H];
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            y0[i] = k0[i] = u0[i] = x0[i] = 0.0;
+            const int64_t idx = (int64_t)(g + i * F::G) * N2 + n2;
+            if (active && idx < M) {
+                const int64_t q = pos_of(P, idx);
+                y0[i] = in.y[q];
+                if (comb && in.kc) k0[i] = in.kc[q];
+                u0[i] = Ua[q];
+                x0[i] = Va[q];
+            }
+        }
 #pragma unroll
         for (int i = 0; i < F::E; ++i) {
             v[i] = czero<C>();
-            if (i < F::E / 2 && active) {
+            if (i < H && active) {
                 const int64_t idx = (int64_t)(g + i * F::G) * N2 + n2;
                 if (idx < M) {
-                    const int64_t q = pos_of(P, idx);
-                    double yv = in.y[q];
+                    double yv = y0[i];
                     if (comb) {
-                        if (in.kc) yv = fma(in.c, in.kc[q], yv);
-                        if (in.ywrite && al == 0) in.ywrite[q] = yv;
+                        if (in.kc) yv = fma(in.c, k0[i], yv);
+                        if (in.ywrite && al == 0) in.ywrite[pos_of(P, idx)] = yv;
                     }
-                    const double u = Ua[q] * yv, x = Va[q] * yv;
+                    const double u = u0[i] * yv, x = x0[i] * yv;
                     if (idx < M - 1) v[i] = from_cd<C>(cd{u, x});
                     if (comb) {
                         const double s = (double)(idx + 1);
@@ -207,16 +222,10 @@ struct PhaseA {
         C *wl = lds + w * 64 * F::E;
         if (active) {
             wave_fft<N1, false>(v, wl + f * N1, g, tw);
-            wave_sync();
+            // spectra are stored column by column: one contiguous run per column
+            C *Za = (C *)P.Z + ((int64_t)al << P.logL) + (int64_t)n2 * N1;
 #pragma unroll
-            for (int i = 0; i < F::E; ++i) wl[f * N1 + g + i * F::G] = cmul(v[i], t4[i]);
-        }
-        __syncthreads();
-        // store rows of GA consecutive columns
-        C *Za = (C *)P.Z + ((int64_t)al << P.logL) + grp * GA;
-        for (int e = tid; e < GA * N1; e += NT) {
-            const int c = e % GA, k1 = e / GA;
-            Za[(int64_t)k1 * N2 + c] = lds[(c / COLS) * 64 * F::E + (c % COLS) * N1 + k1];
+            for (int i = 0; i < F::E; ++i) Za[g + i * F::G] = cmul(v[i], t4[i]);
         }
         if (comb) {
             sw = wave_sum(sw);
@@ -270,10 +279,11 @@ struct PhaseB {
                 const int m = slot >> 1, which = slot & 1;
                 if (m < na && !(single && which)) {
                     const int krow = which ? k1p : k1;
-                    const C *src = (const C *)P.Z + ((int64_t)(a0 + m) << P.logL) + (int64_t)krow * N2;
+                    // row krow of the column-major spectra: stride N1
+                    const C *src = (const C *)P.Z + ((int64_t)(a0 + m) << P.logL) + krow;
                     C v[F::E];
 #pragma unroll
-                    for (int i = 0; i < F::E; ++i) v[i] = src[g + i * F::G];
+                    for (int i = 0; i < F::E; ++i) v[i] = src[(int64_t)(g + i * F::G) * N1];
                     wave_fft<N2, false>(v, rows + slot * N2, g, twf);
                     wave_sync();
 #pragma unroll
@@ -417,6 +427,40 @@ struct PhaseC {
                 }
             }
         }
+        // ---- uniform inputs, loaded before any store: the death-rate
+        // factors w_alpha and, in the last unit, everything size 1 needs
+        // (monomer balance with the shattering gains)
+        double wred[RPRE];
+#pragma unroll
+        for (int a = 0; a < RPRE; ++a) wred[a] = a < rp ? P.red[4 * a] : 0.0;
+        const bool last = unit == units() - 1;
+        double S1 = 0.0, y1 = 0.0, n1v = 0.0, k1v[KMAX];
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) k1v[k] = 0.0;
+        if (last) {
+            y1 = ep.y[0];
+            if (need_n) n1v = ep.n[0];
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k)
+                if (k < nk && ep.coef[k] != 0.0) k1v[k] = ep.ks[k][0];
+            double d1 = 0.0, g1 = 0.0, pairs = 0.0;
+            for (int al = 0; al < R; ++al) {
+                const double wv = P.red[4 * al], t = P.red[4 * al + 1];
+                const double r = P.red[4 * al + 2], pp = P.red[4 * al + 3];
+                const double u1 = P.U[(int64_t)al * P.ustride];
+                const double q = wv - P.V[(int64_t)al * P.ustride] * y1;
+                d1 = fma(u1, wv, d1);
+                g1 = fma(u1, t, g1);
+                pairs = fma(pp, q, fma(r, t, pairs));
+            }
+            S1 = -y1 * d1 + 0.5 * lam * pairs + lam * y1 * g1;
+        }
+        // ---- inputs of this wave slot's first column-pass transform
+        ColPre pre;
+        if constexpr (FUSE) {
+            const int job = w * F::B + lane / F::G;
+            if (job < 2 * COLS * R) col_load(P, unit, job, pre);
+        }
         // ---- inverse DFT over k1 of this unit's packed columns (wave 0)
         if (w == 0) {
             const int f = lane / F::G, g = lane % F::G;
@@ -453,7 +497,7 @@ struct PhaseC {
                 double dsum = 0.0;
 #pragma unroll
                 for (int a = 0; a < RPRE; ++a)
-                    if (a < rp) dsum = fma(Uv[j][a], P.red[4 * a], dsum);
+                    if (a < rp) dsum = fma(Uv[j][a], wred[a], dsum);
                 for (int a = RPRE; a < R; ++a)
                     dsum = fma(P.U[(int64_t)a * P.ustride + qv[j]], P.red[4 * a], dsum);
                 const double S = fma(-(1.0 + lam) * yv[j], dsum, 0.5 * c);
@@ -461,26 +505,9 @@ struct PhaseC {
             }
         }
         // ---- size 1 (index 0): monomer balance with the shattering gains
-        const bool mono = unit == units() - 1 && tid == 0;
+        const bool mono = last && tid == 0;
         double yn1 = 0.0;
-        if (mono) {
-            const double y1 = ep.y[0];
-            double d1 = 0.0, g1 = 0.0, pairs = 0.0;
-            for (int al = 0; al < R; ++al) {
-                const double wv = P.red[4 * al], t = P.red[4 * al + 1];
-                const double r = P.red[4 * al + 2], pp = P.red[4 * al + 3];
-                const double u1 = P.U[(int64_t)al * P.ustride];
-                const double q = wv - P.V[(int64_t)al * P.ustride] * y1;
-                d1 = fma(u1, wv, d1);
-                g1 = fma(u1, t, g1);
-                pairs = fma(pp, q, fma(r, t, pairs));
-            }
-            const double S1 = -y1 * d1 + 0.5 * lam * pairs + lam * y1 * g1;
-            double k1v[KMAX];
-#pragma unroll
-            for (int k = 0; k < KMAX; ++k) k1v[k] = (k < nk && ep.coef[k] != 0.0) ? ep.ks[k][0] : 0.0;
-            yn1 = finish(ep, 0, 1.0, S1, y1, need_n ? ep.n[0] : 0.0, k1v, nk, acc);
-        }
+        if (mono) yn1 = finish(ep, 0, 1.0, S1, y1, n1v, k1v, nk, acc);
         double *ycol = (double *)(lds + W * 64 * F::E);
         if constexpr (FUSE) {
             // next stage state by (local column, row) for the column pass below
@@ -553,29 +580,62 @@ struct PhaseC {
         }
         if constexpr (FUSE) {
             __syncthreads();
-            column_pass(P, unit, lds, ycol);
+            column_pass(P, unit, lds, ycol, pre);
         }
     }
 
     // The next stage's column pass over this unit's 2 COLS columns x R ranks
     // (same arithmetic as phase A given y), one transform per wave slot.
-    __device__ static void column_pass(const RhsPlanDev &P, int unit, C *lds, const double *ycol)
+    // Everything a slot's first transform reads besides y (factors U, V,
+    // twiddles) is loaded at kernel entry, so that pass starts as soon as the
+    // finish has written y.
+    struct ColPre {
+        FftTw<N1, false, C, E> tw;
+        C t4[F::E];
+        double u[F::E / 2], x[F::E / 2];
+    };
+    __device__ static void col_job(const RhsPlanDev &P, int unit, int job, int &jj, int &al, int &n2)
+    {
+        jj = job % (2 * COLS);
+        al = job / (2 * COLS);
+        const int hh = jj / COLS, fc = jj % COLS;
+        n2 = (unit * COLS + fc + 1 + hh * HALF) & (N2 - 1);
+    }
+
+    __device__ static void col_load(const RhsPlanDev &P, int unit, int job, ColPre &pre)
+    {
+        const int lane = lane_id(), g = lane % F::G;
+        int jj, al, n2;
+        col_job(P, unit, job, jj, al, n2);
+        const double *Ua = P.U + (int64_t)al * P.ustride, *Va = P.V + (int64_t)al * P.ustride;
+        pre.tw.load(g, P.rt);
+        step_twiddles<F::E, false>(P.rt, P.logL, (uint32_t)n2, g, F::G, pre.t4);
+#pragma unroll
+        for (int i = 0; i < F::E / 2; ++i) {
+            const int n1 = g + i * F::G;
+            const int64_t idx = (int64_t)n1 * N2 + n2;
+            pre.u[i] = pre.x[i] = 0.0;
+            if (idx < P.M - 1) {
+                const int64_t q = pos_of(P, idx);
+                pre.u[i] = Ua[q];
+                pre.x[i] = Va[q];
+            }
+        }
+    }
+
+    __device__ static void column_pass(const RhsPlanDev &P, int unit, C *lds, const double *ycol,
+                                       ColPre &pre)
     {
         const int lane = lane_id(), w = wave_id();
         const int f = lane / F::G, g = lane % F::G;
         const int64_t M = P.M;
-        FftTw<N1, false, C, E> tw;
-        tw.load(g, P.rt);
         const int nj = 2 * COLS * P.R;
         for (int r0 = 0; r0 < nj; r0 += W * F::B) {
             const int job = r0 + w * F::B + f;
             if (job < nj) {
-                const int jj = job % (2 * COLS), al = job / (2 * COLS);
-                const int hh = jj / COLS, fc = jj % COLS;
-                const int n2 = (unit * COLS + fc + 1 + hh * HALF) & (N2 - 1);
-                const double *Ua = P.U + (int64_t)al * P.ustride, *Va = P.V + (int64_t)al * P.ustride;
-                C t4[F::E];
-                step_twiddles<F::E, false>(P.rt, P.logL, (uint32_t)n2, g, F::G, t4);
+                int jj, al, n2;
+                col_job(P, unit, job, jj, al, n2);
+                if (r0 > 0) col_load(P, unit, job, pre);
                 C v[F::E];
 #pragma unroll
                 for (int i = 0; i < F::E; ++i) {
@@ -585,16 +645,14 @@ struct PhaseC {
                         const int64_t idx = (int64_t)n1 * N2 + n2;
                         if (idx < M - 1) {
                             const double yv = ycol[jj * (N1 / 2) + n1];
-                            const int64_t q = pos_of(P, idx);
-                            v[i] = from_cd<C>(cd{Ua[q] * yv, Va[q] * yv});
+                            v[i] = from_cd<C>(cd{pre.u[i] * yv, pre.x[i] * yv});
                         }
                     }
                 }
-                wave_fft<N1, false>(v, lds + w * 64 * F::E + f * N1, g, tw);
-                C *Za = (C *)P.Z + ((int64_t)al << P.logL) + n2;
+                wave_fft<N1, false>(v, lds + w * 64 * F::E + f * N1, g, pre.tw);
+                C *Za = (C *)P.Z + ((int64_t)al << P.logL) + (int64_t)n2 * N1;
 #pragma unroll
-                for (int i = 0; i < F::E; ++i)
-                    Za[(int64_t)(g + i * F::G) * N2] = cmul(v[i], t4[i]);
+                for (int i = 0; i < F::E; ++i) Za[g + i * F::G] = cmul(v[i], pre.t4[i]);
             }
         }
     }
