@@ -31,13 +31,14 @@ template <class T>
 __global__ __launch_bounds__(SMOL_WG) void kb_A(BatchDev B, int stage)
 {
     extern __shared__ cd lds[];
-    const int b = B.owner[0][blockIdx.x];
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);  // neighbours share an XCD's L2
+    const int b = B.owner[0][blk];
     const IntegDev &I = B.inst[b];
     const IntegCtl c = *I.ctl;  // one snapshot: all fields load together
     if (c.done) return;
     const RhsPlanDev P = plan_of(I, c);
     const Pro in = stage_pro(I, c, c_tab[c.method], stage);
-    const int unit = blockIdx.x - B.first[0][b];
+    const int unit = blk - B.first[0][b];
     switch (B.logL[b]) {
 #define X(LL, A, Bb) \
     case LL: PhaseA<(1 << A), (1 << Bb), T>::run(P, in, unit, (T *)lds); break;
@@ -50,12 +51,13 @@ template <class T>
 __global__ __launch_bounds__(SMOL_WG) void kb_B(BatchDev B, int stage)
 {
     extern __shared__ cd lds[];
-    const int b = B.owner[1][blockIdx.x];
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);  // neighbours share an XCD's L2
+    const int b = B.owner[1][blk];
     const IntegDev &I = B.inst[b];
     const IntegCtl c = *I.ctl;  // one snapshot: all fields load together
     if (c.done) return;
     const RhsPlanDev P = plan_of(I, c);
-    const int unit = blockIdx.x - B.first[1][b];
+    const int unit = blk - B.first[1][b];
     const int logL = B.logL[b];
     if (unit == (1 << ((logL + 1) / 2 - 1)) + 1) {  // N1/2 + 1: the finaliser
         finalize_reductions(P, stage <= 2 ? B.redA[b] : B.nC[b]);
@@ -73,13 +75,14 @@ template <class T, bool FUSE>
 __global__ __launch_bounds__(SMOL_WG) void kb_C(BatchDev B, int stage)
 {
     extern __shared__ cd lds[];
-    const int b = B.owner[2][blockIdx.x];
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);  // neighbours share an XCD's L2
+    const int b = B.owner[2][blk];
     const IntegDev &I = B.inst[b];
     const IntegCtl c = *I.ctl;  // one snapshot: all fields load together
     if (c.done) return;
     const RhsPlanDev P = plan_of(I, c);
     const Epi ep = stage_epi(I, c, c_tab[c.method], stage);
-    const int unit = blockIdx.x - B.first[2][b];
+    const int unit = blk - B.first[2][b];
     switch (B.logL[b]) {
 #define X(LL, A, Bb) \
     case LL: PhaseC<(1 << A), (1 << Bb), T>::template run<FUSE>(P, ep, unit, (T *)lds); break;

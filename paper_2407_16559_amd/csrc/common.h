@@ -70,12 +70,47 @@ __device__ __forceinline__ void wave_sync()
 }
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+// Map workgroup b to a logical index so that consecutive logical indices land
+// on the same XCD (workgroups are dealt round-robin over the 8 XCDs, each with
+// its own L2): the first nb - nb % 8 workgroups are remapped, the rest kept.
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    const int full = nb & ~7;
+    if (b >= full) return b;
+    return (b % 8) * (full / 8) + b / 8;
+}
 __device__ __forceinline__ int wave_id() { return (int)(threadIdx.x >> 6); }
 
-// Deterministic wave-wide sum (fixed butterfly order).
+// Lane exchanges of a double without LDS traffic: ds_swizzle in bit mode
+// (lane i reads lane ((i & 31) ^ X) of its 32-lane half; pattern 0x1F | X << 10)
+// and DPP quad permutations (CTRL = quad_perm code).
+template <int PAT>
+__device__ __forceinline__ double swizzle_d(double v)
+{
+    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), PAT);
+    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), PAT);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Deterministic wave-wide sum: the xor butterfly over lane offsets 32, 16,
+// 8, 4, 2, 1 (each lane adds its partner's value to its own).  Offset 32
+// goes through a lane permute, 16..4 through ds_swizzle, 2 and 1 through
+// DPP quad permutations [2,3,0,1] and [1,0,3,2].
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    v += __shfl_xor(v, 32, 64);
+    v += swizzle_d<0x1F | (16 << 10)>(v);
+    v += swizzle_d<0x1F | (8 << 10)>(v);
+    v += swizzle_d<0x1F | (4 << 10)>(v);
+    v += dpp_d<0x4E>(v);
+    v += dpp_d<0xB1>(v);
     return v;
 }

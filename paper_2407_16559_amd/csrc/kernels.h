@@ -5,16 +5,6 @@
 #pragma once
 #include "sched.h"
 
-// Map workgroup b to a logical index so that consecutive logical indices land
-// on the same XCD (workgroups are dealt round-robin over the 8 XCDs, each with
-// its own L2): the first nb - nb % 8 workgroups are remapped, the rest kept.
-__device__ __forceinline__ int xcd_remap(int b, int nb)
-{
-    const int full = nb & ~7;
-    if (b >= full) return b;
-    return (b % 8) * (full / 8) + b / 8;
-}
-
 // ---- plain right-hand side -------------------------------------------------
 
 template <int N1, int N2, class T, int E, int W>
@@ -48,13 +38,15 @@ __global__ __launch_bounds__(64 * W) void k_phaseC(RhsPlanDev P, Epi ep, int nun
 
 // ---- integrator stages: the same phases, buffers from the control block ----
 
+// method: the run's tableau, passed by the host so that the coefficient
+// loads do not wait for the control block
 template <int N1, int N2, class T, int E, int W>
-__global__ __launch_bounds__(64 * W) void k_int_A(IntegDev I, int stage, int nunits)
+__global__ __launch_bounds__(64 * W) void k_int_A(IntegDev I, int stage, int nunits, int method)
 {
     const IntegCtl c = *I.ctl;  // one snapshot: all fields load together
     if (c.done) return;
     extern __shared__ cd lds[];
-    const Tableau &tab = c_tab[c.method];
+    const Tableau &tab = c_tab[method];
     const RhsPlanDev P = plan_of(I, c);
     const Pro in = stage_pro(I, c, tab, stage);
     const int unit = xcd_remap(blockIdx.x, gridDim.x);
@@ -79,12 +71,12 @@ __global__ __launch_bounds__(64 * W) void k_int_B(IntegDev I, int stage, int job
 }
 
 template <int N1, int N2, class T, int E, int W, bool FUSE>
-__global__ __launch_bounds__(64 * W) void k_int_C(IntegDev I, int stage, int nunits)
+__global__ __launch_bounds__(64 * W) void k_int_C(IntegDev I, int stage, int nunits, int method)
 {
     const IntegCtl c = *I.ctl;  // one snapshot: all fields load together
     if (c.done) return;
     extern __shared__ cd lds[];
-    const Tableau &tab = c_tab[c.method];
+    const Tableau &tab = c_tab[method];
     const RhsPlanDev P = plan_of(I, c);
     const Epi ep = stage_epi(I, c, tab, stage);
     const int unit = xcd_remap(blockIdx.x, gridDim.x);
@@ -127,12 +119,12 @@ struct RhsC {
 };
 struct IntA {
     template <int N1, int N2, class T, int E, int W>
-    static int run(const IntegDev &I, int stage, hipStream_t s)
+    static int run(const IntegDev &I, int stage, int method, hipStream_t s)
     {
         using A = PhaseA<N1, N2, T, E, W>;
         const int n = A::units(I.R);
         hipLaunchKernelGGL((k_int_A<N1, N2, T, E, W>), dim3(n), dim3(A::NT), sizeof(cd) * A::LDS,
-                           s, I, stage, n);
+                           s, I, stage, n, method);
         return SMOL_OK;
     }
 };
@@ -148,16 +140,16 @@ struct IntB {
 };
 struct IntC {
     template <int N1, int N2, class T, int E, int W>
-    static int run(const IntegDev &I, int stage, bool fuse, hipStream_t s)
+    static int run(const IntegDev &I, int stage, bool fuse, int method, hipStream_t s)
     {
         using C = PhaseC<N1, N2, T, E, W>;
         const int n = C::units();
         if (fuse)
             hipLaunchKernelGGL((k_int_C<N1, N2, T, E, W, true>), dim3(n), dim3(C::NT),
-                               sizeof(cd) * C::LDS_FUSE, s, I, stage, n);
+                               sizeof(cd) * C::LDS_FUSE, s, I, stage, n, method);
         else
             hipLaunchKernelGGL((k_int_C<N1, N2, T, E, W, false>), dim3(n), dim3(C::NT),
-                               sizeof(cd) * C::LDS, s, I, stage, n);
+                               sizeof(cd) * C::LDS, s, I, stage, n, method);
         return SMOL_OK;
     }
 };

@@ -8,7 +8,7 @@ SMOL_HIDDEN int launch_rhs_A(int logL, int precision, int v, const RhsPlanDev &P
 }
 
 SMOL_HIDDEN int launch_int_A(int logL, int precision, int v, const IntegDev &I, int stage,
-                             hipStream_t s)
+                             int method, hipStream_t s)
 {
-    return with_variant<IntA, PH_A>(logL, precision, v, I, stage, s);
+    return with_variant<IntA, PH_A>(logL, precision, v, I, stage, method, s);
 }

@@ -9,7 +9,7 @@ SMOL_HIDDEN int launch_rhs_C(int logL, int precision, int v, const RhsPlanDev &P
 }
 
 SMOL_HIDDEN int launch_int_C(int logL, int precision, int v, bool fuse, const IntegDev &I,
-                             int stage, hipStream_t s)
+                             int stage, int method, hipStream_t s)
 {
-    return with_variant<IntC, PH_C>(logL, precision, v, I, stage, fuse, s);
+    return with_variant<IntC, PH_C>(logL, precision, v, I, stage, fuse, method, s);
 }

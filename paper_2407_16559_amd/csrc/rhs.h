@@ -271,6 +271,15 @@ struct PhaseB {
         C *P1 = lds + SLOTS * N2, *P2 = P1 + N2;
         FftTw<N2, false, C, E> twf;
         twf.load(g, P.rt);
+        // twiddles of the two inverse row transforms (slots 0 and 1), loaded
+        // now so that the inverse pass does not wait on a table read
+        const bool inv = slot < (single ? 1 : 2);
+        FftTw<N2, true, C, E> twi;
+        C t4[F::E];
+        if (inv) {
+            twi.load(g, P.rt);
+            step_twiddles<F::E, true>(P.rt, P.logL, (uint32_t)(slot ? k1p : k1), g, F::G, t4);
+        }
         for (int k2 = tid; k2 < N2; k2 += NT) P1[k2] = czero<C>();
         for (int a0 = 0; a0 < P.R; a0 += AL_PER_ROUND) {
             const int na = min(AL_PER_ROUND, P.R - a0);
@@ -312,12 +321,8 @@ struct PhaseB {
         }
         __syncthreads();
         // inverse DFT over k2 of rows k1 (slot 0) and N1-k1 (slot 1)
-        if (slot < (single ? 1 : 2)) {
+        if (inv) {
             const int krow = slot ? k1p : k1;
-            FftTw<N2, true, C, E> twi;
-            twi.load(g, P.rt);
-            C t4[F::E];
-            step_twiddles<F::E, true>(P.rt, P.logL, (uint32_t)krow, g, F::G, t4);
             const C *src = slot ? P2 : P1;
             C v[F::E];
 #pragma unroll
@@ -558,9 +563,10 @@ struct PhaseC {
                     for (int a = 0; a < 4 && a0 + a < R; ++a)
                         s4[4 * a] += P.V[(int64_t)(a0 + a) * P.ustride] * yn1;
                 const int na = (R - a0) < 4 ? (R - a0) : 4;
+                // all 16 sums unconditionally: independent butterflies
+                // interleave, where guarded ones would run one after another
 #pragma unroll
-                for (int k = 0; k < 16; ++k)
-                    if (k < 4 * na) s4[k] = wave_sum(s4[k]);
+                for (int k = 0; k < 16; ++k) s4[k] = wave_sum(s4[k]);
                 if (lane == 0)
                     for (int k = 0; k < 4 * na; ++k) sh[w * 16 + k] = s4[k];
                 __syncthreads();

@@ -142,8 +142,8 @@ SMOL_HIDDEN int launch_rhs_B(int logL, int precision, int v, const RhsPlanDev &P
 SMOL_HIDDEN int launch_rhs_C(int logL, int precision, int v, const RhsPlanDev &P, const Epi &ep,
                              hipStream_t s);
 SMOL_HIDDEN int launch_int_A(int logL, int precision, int v, const IntegDev &I, int stage,
-                             hipStream_t s);
+                             int method, hipStream_t s);
 SMOL_HIDDEN int launch_int_B(int logL, int precision, int v, const IntegDev &I, int stage,
                              int jobs_a, int jobs_c, hipStream_t s);
 SMOL_HIDDEN int launch_int_C(int logL, int precision, int v, bool fuse, const IntegDev &I,
-                             int stage, hipStream_t s);
+                             int stage, int method, hipStream_t s);

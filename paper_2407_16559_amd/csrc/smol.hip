@@ -243,14 +243,15 @@ int launch_rhs(const Plan *p, const RhsPlanDev &P, const Pro &in, const Epi &ep,
 // run A, B, C; from stage 3 on the column pass was done by the previous
 // stage's fused finish, so only B and C run; the finish of stages
 // 2..S-1 is fused with the next column pass.
-int launch_stage(const Plan *p, const IntegDev &I, int stage, int S, hipStream_t s)
+int launch_stage(const Plan *p, const IntegDev &I, int method, int stage, int S, hipStream_t s)
 {
     int rc;
-    if (stage <= 2 && (rc = launch_int_A(p->logL, p->precision, p->var[0], I, stage, s))) return rc;
+    if (stage <= 2 && (rc = launch_int_A(p->logL, p->precision, p->var[0], I, stage, method, s)))
+        return rc;
     if ((rc = launch_int_B(p->logL, p->precision, p->var[1], I, stage, p->dA.jobs, p->dC.jobs, s)))
         return rc;
     const bool fuse = stage >= 2 && stage < S;
-    if ((rc = launch_int_C(p->logL, p->precision, p->var[2], fuse, I, stage, s))) return rc;
+    if ((rc = launch_int_C(p->logL, p->precision, p->var[2], fuse, I, stage, method, s))) return rc;
     HIP_TRY(hipGetLastError());
     return SMOL_OK;
 }
@@ -307,7 +308,8 @@ int get_step_graph(Plan *p, const IntegDev &I, int method, hipGraphExec_t *out)
     int rc = SMOL_OK;
     const int nC = p->dC.jobs;
     for (int a = 0; a < SMOL_GRAPH_ATTEMPTS; ++a) {
-        for (int st = 2; st <= S && rc == SMOL_OK; ++st) rc = launch_stage(p, I, st, S, p->cap);
+        for (int st = 2; st <= S && rc == SMOL_OK; ++st)
+            rc = launch_stage(p, I, method, st, S, p->cap);
         hipLaunchKernelGGL(k_ctrl, dim3(1), dim3(SMOL_WG), 0, p->cap, I, nC);
     }
     hipError_t e = hipStreamEndCapture(p->cap, &g);
@@ -474,10 +476,10 @@ extern "C" int smol_integrate_ex(int64_t M, int32_t R, const double *U, const do
     hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, n0, I.nb[0], M, 1, M, I.Mt, p->logL);
     const int nC = p->dC.jobs;
     // starting step: S(n0), h0, S(n0 + h0 f0), h
-    if ((rc = launch_stage(p, I, 0, 0, s))) return rc;
+    if ((rc = launch_stage(p, I, method, 0, 0, s))) return rc;
     hipLaunchKernelGGL(k_init_h0, dim3(1), dim3(SMOL_WG), 0, s, I, nC);
     if (!(o.h0 > 0)) {
-        if ((rc = launch_stage(p, I, 1, 0, s))) return rc;
+        if ((rc = launch_stage(p, I, method, 1, 0, s))) return rc;
         hipLaunchKernelGGL(k_init_h, dim3(1), dim3(SMOL_WG), 0, s, I, nC);
     }
     HIP_TRY(hipGetLastError());
