@@ -8,88 +8,15 @@
 // return at entry).  With hundreds of instances each launch holds tens of
 // thousands of workgroups, which fills the chip and hides memory latency
 // that a single small instance cannot.
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
-#include "host.h"
+#include "sched.h"
 
-struct BatchDev {
-    const IntegDev *inst;   // per instance
-    const int *logL;        // per instance
-    const int *first[3];    // first block of each instance per kernel A, B, C
-    const int *owner[3];    // instance of each block per kernel
-    const int *nC;          // finish units per instance
-    const int *redA;        // column-pass reduction jobs per instance
-    const int *active;      // instances still running (one controller workgroup each)
-};
-
-#define SMOL_SHAPES(X) \
-    X(6, 3, 3) X(7, 4, 3) X(8, 4, 4) X(9, 5, 4) X(10, 5, 5) X(11, 6, 5) X(12, 6, 6) X(13, 7, 6) \
-    X(14, 7, 7) X(15, 8, 7) X(16, 8, 8) X(17, 9, 8) X(18, 9, 9) X(19, 10, 9) X(20, 10, 10)
-
-template <class T>
-__global__ __launch_bounds__(SMOL_WG) void kb_A(BatchDev B, int stage)
-{
-    extern __shared__ cd lds[];
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);  // neighbours share an XCD's L2
-    const int b = B.owner[0][blk];
-    const IntegDev &I = B.inst[b];
-    const IntegCtl c = *I.ctl;  // one snapshot: all fields load together
-    if (c.done) return;
-    const RhsPlanDev P = plan_of(I, c);
-    const Pro in = stage_pro(I, c, c_tab[c.method], stage);
-    const int unit = blk - B.first[0][b];
-    switch (B.logL[b]) {
-#define X(LL, A, Bb) \
-    case LL: PhaseA<(1 << A), (1 << Bb), T>::run(P, in, unit, (T *)lds); break;
-        SMOL_SHAPES(X)
-#undef X
-    }
-}
-
-template <class T>
-__global__ __launch_bounds__(SMOL_WG) void kb_B(BatchDev B, int stage)
-{
-    extern __shared__ cd lds[];
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);  // neighbours share an XCD's L2
-    const int b = B.owner[1][blk];
-    const IntegDev &I = B.inst[b];
-    const IntegCtl c = *I.ctl;  // one snapshot: all fields load together
-    if (c.done) return;
-    const RhsPlanDev P = plan_of(I, c);
-    const int unit = blk - B.first[1][b];
-    const int logL = B.logL[b];
-    if (unit == (1 << ((logL + 1) / 2 - 1)) + 1) {  // N1/2 + 1: the finaliser
-        finalize_reductions(P, stage <= 2 ? B.redA[b] : B.nC[b]);
-        return;
-    }
-    switch (logL) {
-#define X(LL, A, Bb) \
-    case LL: PhaseB<(1 << A), (1 << Bb), T>::run(P, unit, (T *)lds); break;
-        SMOL_SHAPES(X)
-#undef X
-    }
-}
-
-template <class T, bool FUSE>
-__global__ __launch_bounds__(SMOL_WG) void kb_C(BatchDev B, int stage)
-{
-    extern __shared__ cd lds[];
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);  // neighbours share an XCD's L2
-    const int b = B.owner[2][blk];
-    const IntegDev &I = B.inst[b];
-    const IntegCtl c = *I.ctl;  // one snapshot: all fields load together
-    if (c.done) return;
-    const RhsPlanDev P = plan_of(I, c);
-    const Epi ep = stage_epi(I, c, c_tab[c.method], stage);
-    const int unit = blk - B.first[2][b];
-    switch (B.logL[b]) {
-#define X(LL, A, Bb) \
-    case LL: PhaseC<(1 << A), (1 << Bb), T>::template run<FUSE>(P, ep, unit, (T *)lds); break;
-        SMOL_SHAPES(X)
-#undef X
-    }
-}
+// The batched phase kernels (one launch per transform shape and phase over
+// that shape's instances, under the shape's launch schedule) live with the
+// single-instance ones in phases_a/b/c.hip.
 
 // one workgroup per listed instance
 __global__ __launch_bounds__(SMOL_WG) void kb_init_h0(BatchDev B)
@@ -111,43 +38,61 @@ __global__ __launch_bounds__(SMOL_WG) void kb_ctrl(BatchDev B)
 namespace {
 
 struct BatchRun {
-    int n = 0;
-    std::vector<int> logL, units[3], ldsn[4];  // ldsn[3]: fused finish
-    std::vector<size_t> off;     // arena offset of each instance
-    int total[3] = {0, 0, 0};    // blocks of each kernel over the listed instances
-    int nact = 0;                // listed instances
-    size_t lds[4] = {0, 0, 0, 0};
+    int n = 0, precision = 0;
+    std::vector<int> logL, units[3];  // per instance
+    std::vector<size_t> off;          // arena offset of each instance
+    int nact = 0;                     // listed instances
+    // shapes of the listed instances: schedule, grids, LDS
+    struct Shape {
+        int logL;
+        int var[3];
+        int base[3], count[3];
+        size_t lds[3], lds_fused;
+    };
+    std::vector<Shape> shapes;
 };
 
-// Block-to-instance tables over the instances in `ids` (device buffers
-// sized for all instances are reused).
-int build_tables(BatchRun &br, const std::vector<int> &ids, int *dfirst[3], int *downer[3],
+// Block-to-instance tables over the instances in `ids`, grouped by shape
+// (device buffers sized for all instances are reused).
+int build_tables(BatchRun &br, std::vector<int> ids, int *dfirst[3], int *downer[3],
                  int *dactive, hipStream_t s)
 {
+    std::stable_sort(ids.begin(), ids.end(),
+                     [&](int x, int y) { return br.logL[x] < br.logL[y]; });
     std::vector<int> first[3], owner[3];
-    for (int k = 0; k < 3; ++k) {
-        first[k].assign(br.n + 1, 0);
-        br.total[k] = 0;
-        br.lds[k] = 0;
-    }
-    br.lds[3] = 0;
+    for (int k = 0; k < 3; ++k) first[k].assign(br.n + 1, 0);
+    br.shapes.clear();
+    int total[3] = {0, 0, 0};
     for (int i : ids) {
-        const size_t lf = sizeof(cd) * (size_t)br.ldsn[3][i];
-        if (lf > br.lds[3]) br.lds[3] = lf;
+        if (br.shapes.empty() || br.shapes.back().logL != br.logL[i]) {
+            BatchRun::Shape sh{};
+            sh.logL = br.logL[i];
+            schedule_of(sh.logL, br.precision, sh.var);
+            PhaseDims d;
+            for (int k = 0; k < 3; ++k) {
+                sh.base[k] = total[k];
+                int rc = phase_dims(sh.logL, br.precision, k, sh.var[k], 1, false, &d);
+                if (rc) return rc;
+                sh.lds[k] = d.lds_bytes;
+            }
+            int rc = phase_dims(sh.logL, br.precision, PH_C, sh.var[2], 1, true, &d);
+            if (rc) return rc;
+            sh.lds_fused = d.lds_bytes;
+            br.shapes.push_back(sh);
+        }
         for (int k = 0; k < 3; ++k) {
-            first[k][i] = br.total[k];
+            first[k][i] = total[k];
             for (int j = 0; j < br.units[k][i]; ++j) owner[k].push_back(i);
-            br.total[k] += br.units[k][i];
-            const size_t lb = sizeof(cd) * (size_t)br.ldsn[k][i];
-            if (lb > br.lds[k]) br.lds[k] = lb;
+            total[k] += br.units[k][i];
+            br.shapes.back().count[k] = total[k] - br.shapes.back().base[k];
         }
     }
     br.nact = (int)ids.size();
     for (int k = 0; k < 3; ++k) {
         HIP_TRY(hipMemcpyAsync(dfirst[k], first[k].data(), sizeof(int) * (br.n + 1),
                                hipMemcpyHostToDevice, s));
-        if (br.total[k])
-            HIP_TRY(hipMemcpyAsync(downer[k], owner[k].data(), sizeof(int) * br.total[k],
+        if (total[k])
+            HIP_TRY(hipMemcpyAsync(downer[k], owner[k].data(), sizeof(int) * total[k],
                                    hipMemcpyHostToDevice, s));
     }
     HIP_TRY(hipMemcpyAsync(dactive, ids.data(), sizeof(int) * ids.size(), hipMemcpyHostToDevice, s));
@@ -157,27 +102,28 @@ int build_tables(BatchRun &br, const std::vector<int> &ids, int *dfirst[3], int 
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Same kernel sequence as a single instance: A only up to stage 2, the
-// finish of stages 2..S-1 fused with the next column pass.
-template <class T>
-void launch_stage(const BatchDev &B, const BatchRun &br, int stage, int S, hipStream_t s)
+// Same kernel sequence as a single instance (A only up to stage 2, the
+// finish of stages 2..S-1 fused with the next column pass), each kernel as
+// one launch per shape over that shape's instances, under its schedule.
+int launch_stage(const BatchDev &B, const BatchRun &br, int method, int stage, int S,
+                 hipStream_t s)
 {
+    int rc;
+    const int p = br.precision;
     if (stage <= 2)
-        hipLaunchKernelGGL(kb_A<T>, dim3(br.total[0]), dim3(SMOL_WG), br.lds[0], s, B, stage);
-    hipLaunchKernelGGL(kb_B<T>, dim3(br.total[1]), dim3(SMOL_WG), br.lds[1], s, B, stage);
-    if (stage >= 2 && stage < S)
-        hipLaunchKernelGGL((kb_C<T, true>), dim3(br.total[2]), dim3(SMOL_WG), br.lds[3], s, B, stage);
-    else
-        hipLaunchKernelGGL((kb_C<T, false>), dim3(br.total[2]), dim3(SMOL_WG), br.lds[2], s, B, stage);
-}
-
-void launch_stage_p(int precision, const BatchDev &B, const BatchRun &br, int stage, int S,
-                    hipStream_t s)
-{
-    if (precision == SMOL_FP32X2)
-        launch_stage<cff>(B, br, stage, S, s);
-    else
-        launch_stage<cd>(B, br, stage, S, s);
+        for (const auto &sh : br.shapes)
+            if (sh.count[0] &&
+                (rc = launch_bat_A(sh.logL, p, sh.var[0], B, sh.base[0], sh.count[0], stage, method, s)))
+                return rc;
+    for (const auto &sh : br.shapes)
+        if (sh.count[1] && (rc = launch_bat_B(sh.logL, p, sh.var[1], B, sh.base[1], sh.count[1], stage, s)))
+            return rc;
+    const bool fuse = stage >= 2 && stage < S;
+    for (const auto &sh : br.shapes)
+        if (sh.count[2] &&
+            (rc = launch_bat_C(sh.logL, p, sh.var[2], B, sh.base[2], sh.count[2], stage, fuse, method, s)))
+            return rc;
+    return SMOL_OK;
 }
 
 }  // namespace
@@ -215,27 +161,27 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
     // ---- sizes and arena layout
     BatchRun br;
     br.n = n_inst;
+    br.precision = precision;
     std::vector<int> nC(n_inst), redA(n_inst);
     br.logL.resize(n_inst);
     br.off.resize(n_inst);
     for (int k = 0; k < 3; ++k) br.units[k].resize(n_inst);
-    for (int k = 0; k < 4; ++k) br.ldsn[k].resize(n_inst);
     size_t at = align256(sizeof(IntegCtl) * n_inst);
     int64_t blocks[3] = {0, 0, 0};
     for (int i = 0; i < n_inst; ++i) {
         const smol_instance &q = inst[i];
         const int logL = fft_log2(q.M);
         br.logL[i] = logL;
-        int u[8];
-        if ((rc = with_shape<ShapeUnits>(logL, precision, (int)q.R, u))) return rc;
+        int var[3];
+        schedule_of(logL, precision, var);
+        PhaseDims d[3];
         for (int k = 0; k < 3; ++k) {
-            br.units[k][i] = u[k];
-            br.ldsn[k][i] = u[4 + k];
-            blocks[k] += u[k];
+            if ((rc = phase_dims(logL, precision, k, var[k], (int)q.R, false, &d[k]))) return rc;
+            br.units[k][i] = d[k].units;
+            blocks[k] += d[k].units;
         }
-        br.ldsn[3][i] = u[7];
-        nC[i] = u[2];
-        redA[i] = u[3];
+        nC[i] = d[PH_C].jobs;
+        redA[i] = d[PH_A].jobs;
         const int64_t L = 1LL << logL, half = L / 2, N2 = 1LL << (logL / 2);
         const int64_t Mt = q.M > half + 1 ? q.M : half + 1;
         br.off[i] = at;
@@ -381,10 +327,10 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
         }
         if (!ids.empty() && (rc = build_tables(br, ids, dfirst, downer, dactive, s))) break;
         if (!ids.empty()) {
-            launch_stage_p(precision, B, br, 0, 0, s);
+            if ((rc = launch_stage(B, br, method, 0, 0, s))) break;
             hipLaunchKernelGGL(kb_init_h0, dim3(br.nact), dim3(SMOL_WG), 0, s, B);
             if (!(o.h0 > 0)) {
-                launch_stage_p(precision, B, br, 1, 0, s);
+                if ((rc = launch_stage(B, br, method, 1, 0, s))) break;
                 hipLaunchKernelGGL(kb_init_h, dim3(br.nact), dim3(SMOL_WG), 0, s, B);
             }
         }
@@ -404,7 +350,15 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
             hipGraph_t g;
             HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
             for (int a = 0; a < SMOL_GRAPH_ATTEMPTS; ++a) {
-                for (int st = 2; st <= S; ++st) launch_stage_p(precision, B, br, st, S, cap);
+                for (int st = 2; st <= S; ++st) {
+                    int r = launch_stage(B, br, method, st, S, cap);
+                    if (r) {
+                        hipGraph_t g = nullptr;
+                        (void)hipStreamEndCapture(cap, &g);
+                        if (g) (void)hipGraphDestroy(g);
+                        return r;
+                    }
+                }
                 hipLaunchKernelGGL(kb_ctrl, dim3(br.nact), dim3(SMOL_WG), 0, cap, B);
             }
             HIP_TRY(hipStreamEndCapture(cap, &g));

@@ -165,6 +165,19 @@ __device__ inline Epi stage_epi(const IntegDev &I, const IntegCtl &c, const Tabl
     return ep;
 }
 
+// Device tables of a batched run.  Instances are grouped by transform shape;
+// each kernel's workgroups over a shape's instances are contiguous, so one
+// launch per shape covers blocks [base, base + count).
+struct BatchDev {
+    const IntegDev *inst;   // per instance
+    const int *logL;        // per instance
+    const int *first[3];    // first block of each instance per kernel A, B, C
+    const int *owner[3];    // instance of each block per kernel
+    const int *nC;          // finish units per instance
+    const int *redA;        // column-pass reduction jobs per instance
+    const int *active;      // instances still running (one controller workgroup each)
+};
+
 // Prepare the next attempt (one thread): step-start clamp, limits, t_end clip.
 __device__ inline void prepare_attempt(IntegCtl &c, bool new_step)
 {

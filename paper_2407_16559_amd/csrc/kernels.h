@@ -83,6 +83,54 @@ __global__ __launch_bounds__(64 * W) void k_int_C(IntegDev I, int stage, int nun
     if (unit < nunits) PhaseC<N1, N2, T, E, W>::template run<FUSE>(P, ep, unit, (T *)lds);
 }
 
+// ---- batched stage kernels: blocks [base, base + gridDim) of one shape -------
+
+template <int N1, int N2, class T, int E, int W>
+__global__ __launch_bounds__(64 * W) void kb_A(BatchDev B, int base, int stage, int method)
+{
+    extern __shared__ cd lds[];
+    const int blk = base + xcd_remap(blockIdx.x, gridDim.x);  // neighbours share an XCD
+    const int b = B.owner[0][blk];
+    const IntegDev &I = B.inst[b];
+    const IntegCtl c = *I.ctl;
+    if (c.done) return;
+    const RhsPlanDev P = plan_of(I, c);
+    const Pro in = stage_pro(I, c, c_tab[method], stage);
+    PhaseA<N1, N2, T, E, W>::run(P, in, blk - B.first[0][b], (T *)lds);
+}
+
+template <int N1, int N2, class T, int E, int W>
+__global__ __launch_bounds__(64 * W) void kb_B(BatchDev B, int base, int stage)
+{
+    extern __shared__ cd lds[];
+    const int blk = base + xcd_remap(blockIdx.x, gridDim.x);
+    const int b = B.owner[1][blk];
+    const IntegDev &I = B.inst[b];
+    const IntegCtl c = *I.ctl;
+    if (c.done) return;
+    const RhsPlanDev P = plan_of(I, c);
+    const int unit = blk - B.first[1][b];
+    if (unit == PhaseB<N1, N2, T, E, W>::units()) {
+        finalize_reductions<64 * W>(P, stage <= 2 ? B.redA[b] : B.nC[b]);
+        return;
+    }
+    PhaseB<N1, N2, T, E, W>::run(P, unit, (T *)lds);
+}
+
+template <int N1, int N2, class T, int E, int W, bool FUSE>
+__global__ __launch_bounds__(64 * W) void kb_C(BatchDev B, int base, int stage, int method)
+{
+    extern __shared__ cd lds[];
+    const int blk = base + xcd_remap(blockIdx.x, gridDim.x);
+    const int b = B.owner[2][blk];
+    const IntegDev &I = B.inst[b];
+    const IntegCtl c = *I.ctl;
+    if (c.done) return;
+    const RhsPlanDev P = plan_of(I, c);
+    const Epi ep = stage_epi(I, c, c_tab[method], stage);
+    PhaseC<N1, N2, T, E, W>::template run<FUSE>(P, ep, blk - B.first[2][b], (T *)lds);
+}
+
 // ---- launch functors (used through with_variant) ----------------------------
 
 struct RhsA {
@@ -150,6 +198,42 @@ struct IntC {
         else
             hipLaunchKernelGGL((k_int_C<N1, N2, T, E, W, false>), dim3(n), dim3(C::NT),
                                sizeof(cd) * C::LDS, s, I, stage, n, method);
+        return SMOL_OK;
+    }
+};
+
+struct BatA {
+    template <int N1, int N2, class T, int E, int W>
+    static int run(const BatchDev &B, int base, int count, int stage, int method, hipStream_t s)
+    {
+        using A = PhaseA<N1, N2, T, E, W>;
+        hipLaunchKernelGGL((kb_A<N1, N2, T, E, W>), dim3(count), dim3(A::NT), sizeof(cd) * A::LDS,
+                           s, B, base, stage, method);
+        return SMOL_OK;
+    }
+};
+struct BatB {
+    template <int N1, int N2, class T, int E, int W>
+    static int run(const BatchDev &B, int base, int count, int stage, hipStream_t s)
+    {
+        using P = PhaseB<N1, N2, T, E, W>;
+        hipLaunchKernelGGL((kb_B<N1, N2, T, E, W>), dim3(count), dim3(P::NT), sizeof(cd) * P::LDS,
+                           s, B, base, stage);
+        return SMOL_OK;
+    }
+};
+struct BatC {
+    template <int N1, int N2, class T, int E, int W>
+    static int run(const BatchDev &B, int base, int count, int stage, bool fuse, int method,
+                   hipStream_t s)
+    {
+        using C = PhaseC<N1, N2, T, E, W>;
+        if (fuse)
+            hipLaunchKernelGGL((kb_C<N1, N2, T, E, W, true>), dim3(count), dim3(C::NT),
+                               sizeof(cd) * C::LDS_FUSE, s, B, base, stage, method);
+        else
+            hipLaunchKernelGGL((kb_C<N1, N2, T, E, W, false>), dim3(count), dim3(C::NT),
+                               sizeof(cd) * C::LDS, s, B, base, stage, method);
         return SMOL_OK;
     }
 };

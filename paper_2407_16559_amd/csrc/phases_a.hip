@@ -12,3 +12,9 @@ SMOL_HIDDEN int launch_int_A(int logL, int precision, int v, const IntegDev &I, 
 {
     return with_variant<IntA, PH_A>(logL, precision, v, I, stage, method, s);
 }
+
+SMOL_HIDDEN int launch_bat_A(int logL, int precision, int v, const BatchDev &B, int base, int count,
+                             int stage, int method, hipStream_t s)
+{
+    return with_variant<BatA, PH_A>(logL, precision, v, B, base, count, stage, method, s);
+}

@@ -12,3 +12,9 @@ SMOL_HIDDEN int launch_int_B(int logL, int precision, int v, const IntegDev &I, 
 {
     return with_variant<IntB, PH_B>(logL, precision, v, I, stage, jobs_a, jobs_c, s);
 }
+
+SMOL_HIDDEN int launch_bat_B(int logL, int precision, int v, const BatchDev &B, int base, int count,
+                             int stage, hipStream_t s)
+{
+    return with_variant<BatB, PH_B>(logL, precision, v, B, base, count, stage, s);
+}

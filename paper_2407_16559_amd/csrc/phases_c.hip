@@ -13,3 +13,9 @@ SMOL_HIDDEN int launch_int_C(int logL, int precision, int v, bool fuse, const In
 {
     return with_variant<IntC, PH_C>(logL, precision, v, I, stage, fuse, method, s);
 }
+
+SMOL_HIDDEN int launch_bat_C(int logL, int precision, int v, const BatchDev &B, int base, int count,
+                             int stage, bool fuse, int method, hipStream_t s)
+{
+    return with_variant<BatC, PH_C>(logL, precision, v, B, base, count, stage, fuse, method, s);
+}

@@ -147,3 +147,13 @@ SMOL_HIDDEN int launch_int_B(int logL, int precision, int v, const IntegDev &I, 
                              int jobs_a, int jobs_c, hipStream_t s);
 SMOL_HIDDEN int launch_int_C(int logL, int precision, int v, bool fuse, const IntegDev &I,
                              int stage, int method, hipStream_t s);
+// Batched stage kernels over blocks [base, base + count) of one shape.
+SMOL_HIDDEN int launch_bat_A(int logL, int precision, int v, const BatchDev &B, int base,
+                             int count, int stage, int method, hipStream_t s);
+SMOL_HIDDEN int launch_bat_B(int logL, int precision, int v, const BatchDev &B, int base,
+                             int count, int stage, hipStream_t s);
+SMOL_HIDDEN int launch_bat_C(int logL, int precision, int v, const BatchDev &B, int base,
+                             int count, int stage, bool fuse, int method, hipStream_t s);
+// Launch schedule (variants of A, B, C) currently installed for 2^logL
+// (float-float: variant 0); caller holds the library lock.
+SMOL_HIDDEN void schedule_of(int logL, int precision, int *v);

@@ -614,6 +614,13 @@ int set_schedule_locked(int logL, const int32_t *v)
 }
 }  // namespace
 
+SMOL_HIDDEN void schedule_of(int logL, int precision, int *v)
+{
+    sched_init();
+    for (int k = 0; k < 3; ++k)
+        v[k] = (precision == SMOL_FP64 && logL >= 6 && logL <= SMOL_LOG_LMAX) ? g_sched[logL][k] : 0;
+}
+
 extern "C" int smol_set_schedule(int32_t logL, const int32_t *variants)
 {
     std::lock_guard<std::mutex> lk(g_mu);

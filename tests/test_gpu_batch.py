@@ -22,17 +22,6 @@ def smol():
     return smol
 
 
-@pytest.fixture(autouse=True)
-def default_schedule(smol):
-    """Single-instance runs on the default schedule for the exact comparisons."""
-    saved = {L: smol.get_schedule(L) for L in range(12, 21)}
-    for L in saved:
-        smol.set_schedule(L, (0, 0, 0))
-    yield
-    for L, v in saved.items():
-        smol.set_schedule(L, v)
-
-
 def _instances(specs):
     out = []
     for M, a, lam, s0, t_end in specs:
