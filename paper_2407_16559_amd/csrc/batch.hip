@@ -14,6 +14,8 @@
 
 #include "sched.h"
 
+#define SMOL_BATCH_STREAMS 4  // one per hardware queue (the runtime's default count)
+
 // The batched phase kernels (one launch per transform shape and phase over
 // that shape's instances, under the shape's launch schedule) live with the
 // single-instance ones in phases_a/b/c.hip.
@@ -29,9 +31,9 @@ __global__ __launch_bounds__(SMOL_WG) void kb_init_h(BatchDev B)
     const int b = B.active[blockIdx.x];
     init_h_step(B.inst[b], B.nC[b]);
 }
-__global__ __launch_bounds__(SMOL_WG) void kb_ctrl(BatchDev B)
+__global__ __launch_bounds__(SMOL_WG) void kb_ctrl(BatchDev B, int base)
 {
-    const int b = B.active[blockIdx.x];
+    const int b = B.active[base + blockIdx.x];
     controller_step(B.inst[b], B.nC[b]);
 }
 
@@ -46,7 +48,8 @@ struct BatchRun {
     struct Shape {
         int logL;
         int var[3];
-        int base[3], count[3];
+        int base[3], count[3];  // block range of each kernel
+        int abase, acount;      // range in the list of running instances
         size_t lds[3], lds_fused;
     };
     std::vector<Shape> shapes;
@@ -63,7 +66,8 @@ int build_tables(BatchRun &br, std::vector<int> ids, int *dfirst[3], int *downer
     for (int k = 0; k < 3; ++k) first[k].assign(br.n + 1, 0);
     br.shapes.clear();
     int total[3] = {0, 0, 0};
-    for (int i : ids) {
+    for (size_t pos = 0; pos < ids.size(); ++pos) {
+        const int i = ids[pos];
         if (br.shapes.empty() || br.shapes.back().logL != br.logL[i]) {
             BatchRun::Shape sh{};
             sh.logL = br.logL[i];
@@ -78,8 +82,10 @@ int build_tables(BatchRun &br, std::vector<int> ids, int *dfirst[3], int *downer
             int rc = phase_dims(sh.logL, br.precision, PH_C, sh.var[2], 1, true, &d);
             if (rc) return rc;
             sh.lds_fused = d.lds_bytes;
+            sh.abase = (int)pos;
             br.shapes.push_back(sh);
         }
+        br.shapes.back().acount += 1;
         for (int k = 0; k < 3; ++k) {
             first[k][i] = total[k];
             for (int j = 0; j < br.units[k][i]; ++j) owner[k].push_back(i);
@@ -104,25 +110,31 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Same kernel sequence as a single instance (A only up to stage 2, the
 // finish of stages 2..S-1 fused with the next column pass), each kernel as
-// one launch per shape over that shape's instances, under its schedule.
-int launch_stage(const BatchDev &B, const BatchRun &br, int method, int stage, int S,
-                 hipStream_t s)
+// one launch over the instances of one shape, under that shape's schedule.
+int launch_stage(const BatchDev &B, const BatchRun &br, const BatchRun::Shape &sh, int method,
+                 int stage, int S, hipStream_t s)
 {
     int rc;
     const int p = br.precision;
-    if (stage <= 2)
-        for (const auto &sh : br.shapes)
-            if (sh.count[0] &&
-                (rc = launch_bat_A(sh.logL, p, sh.var[0], B, sh.base[0], sh.count[0], stage, method, s)))
-                return rc;
-    for (const auto &sh : br.shapes)
-        if (sh.count[1] && (rc = launch_bat_B(sh.logL, p, sh.var[1], B, sh.base[1], sh.count[1], stage, s)))
-            return rc;
+    if (stage <= 2 && sh.count[0] &&
+        (rc = launch_bat_A(sh.logL, p, sh.var[0], B, sh.base[0], sh.count[0], stage, method, s)))
+        return rc;
+    if (sh.count[1] && (rc = launch_bat_B(sh.logL, p, sh.var[1], B, sh.base[1], sh.count[1], stage, s)))
+        return rc;
     const bool fuse = stage >= 2 && stage < S;
-    for (const auto &sh : br.shapes)
-        if (sh.count[2] &&
-            (rc = launch_bat_C(sh.logL, p, sh.var[2], B, sh.base[2], sh.count[2], stage, fuse, method, s)))
-            return rc;
+    if (sh.count[2] &&
+        (rc = launch_bat_C(sh.logL, p, sh.var[2], B, sh.base[2], sh.count[2], stage, fuse, method, s)))
+        return rc;
+    return SMOL_OK;
+}
+
+int launch_stage_all(const BatchDev &B, const BatchRun &br, int method, int stage, int S,
+                     hipStream_t s)
+{
+    for (const auto &sh : br.shapes) {
+        int rc = launch_stage(B, br, sh, method, stage, S, s);
+        if (rc) return rc;
+    }
     return SMOL_OK;
 }
 
@@ -203,8 +215,8 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
     char *arena = nullptr;
     if (hipMalloc(&arena, arena_bytes) != hipSuccess) return SMOL_ENOMEM;
     IntegCtl *hctl = nullptr;
-    hipStream_t cap = nullptr;
-    hipGraphExec_t ge = nullptr;
+    hipStream_t streams[SMOL_BATCH_STREAMS] = {};
+    std::vector<hipGraphExec_t> ge;
     rc = SMOL_OK;
     do {
         if (hipHostMalloc(&hctl, sizeof(IntegCtl) * n_inst, hipHostMallocDefault) != hipSuccess) {
@@ -327,10 +339,10 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
         }
         if (!ids.empty() && (rc = build_tables(br, ids, dfirst, downer, dactive, s))) break;
         if (!ids.empty()) {
-            if ((rc = launch_stage(B, br, method, 0, 0, s))) break;
+            if ((rc = launch_stage_all(B, br, method, 0, 0, s))) break;
             hipLaunchKernelGGL(kb_init_h0, dim3(br.nact), dim3(SMOL_WG), 0, s, B);
             if (!(o.h0 > 0)) {
-                if ((rc = launch_stage(B, br, method, 1, 0, s))) break;
+                if ((rc = launch_stage_all(B, br, method, 1, 0, s))) break;
                 hipLaunchKernelGGL(kb_init_h, dim3(br.nact), dim3(SMOL_WG), 0, s, B);
             }
         }
@@ -338,35 +350,49 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
             rc = SMOL_EDEVICE;
             break;
         }
-        // ---- graph of SMOL_GRAPH_ATTEMPTS attempts over the listed instances
-        if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+        // ---- one graph of SMOL_GRAPH_ATTEMPTS attempts per shape, each shape
+        // on its own stream (up to SMOL_BATCH_STREAMS, default priority), so
+        // the shapes' independent kernel chains run side by side
+        int nstream = 0;
+        for (; nstream < SMOL_BATCH_STREAMS; ++nstream)
+            if (hipStreamCreateWithFlags(&streams[nstream], hipStreamNonBlocking) != hipSuccess) {
+                rc = SMOL_EDEVICE;
+                break;
+            }
+        if (rc) break;
+        const int S = method == SMOL_DP54 ? 7 : 4;
+        auto capture = [&]() -> int {
+            for (auto &g : ge)
+                if (g) (void)hipGraphExecDestroy(g);
+            ge.assign(br.shapes.size(), nullptr);
+            for (size_t j = 0; j < br.shapes.size(); ++j) {
+                const auto &sh = br.shapes[j];
+                hipStream_t cs = streams[j % nstream];
+                hipGraph_t g = nullptr;
+                HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+                int r = SMOL_OK;
+                for (int a = 0; a < SMOL_GRAPH_ATTEMPTS && r == SMOL_OK; ++a) {
+                    for (int st = 2; st <= S && r == SMOL_OK; ++st)
+                        r = launch_stage(B, br, sh, method, st, S, cs);
+                    hipLaunchKernelGGL(kb_ctrl, dim3(sh.acount), dim3(SMOL_WG), 0, cs, B, sh.abase);
+                }
+                hipError_t e = hipStreamEndCapture(cs, &g);
+                if (r) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return r;
+                }
+                HIP_TRY(e);
+                e = hipGraphInstantiate(&ge[j], g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                HIP_TRY(e);
+            }
+            return SMOL_OK;
+        };
+        // the starting steps were queued on s
+        if (hipStreamSynchronize(s) != hipSuccess) {
             rc = SMOL_EDEVICE;
             break;
         }
-        const int S = method == SMOL_DP54 ? 7 : 4;
-        auto capture = [&]() -> int {
-            if (ge) (void)hipGraphExecDestroy(ge);
-            ge = nullptr;
-            hipGraph_t g;
-            HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-            for (int a = 0; a < SMOL_GRAPH_ATTEMPTS; ++a) {
-                for (int st = 2; st <= S; ++st) {
-                    int r = launch_stage(B, br, method, st, S, cap);
-                    if (r) {
-                        hipGraph_t g = nullptr;
-                        (void)hipStreamEndCapture(cap, &g);
-                        if (g) (void)hipGraphDestroy(g);
-                        return r;
-                    }
-                }
-                hipLaunchKernelGGL(kb_ctrl, dim3(br.nact), dim3(SMOL_WG), 0, cap, B);
-            }
-            HIP_TRY(hipStreamEndCapture(cap, &g));
-            hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            HIP_TRY(e);
-            return SMOL_OK;
-        };
         // ---- replay until every instance is done; when the running set
         // halves, rebuild the tables over it and capture again, so finished
         // instances stop costing workgroups
@@ -377,8 +403,11 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
                 if ((rc = capture())) break;
                 need_capture = false;
             }
-            for (int64_t k = 0; k < chunk && rc == SMOL_OK; ++k)
-                if (hipGraphLaunch(ge, s) != hipSuccess) rc = SMOL_EDEVICE;
+            for (size_t j = 0; j < ge.size() && rc == SMOL_OK; ++j)
+                for (int64_t k = 0; k < chunk && rc == SMOL_OK; ++k)
+                    if (hipGraphLaunch(ge[j], streams[j % nstream]) != hipSuccess) rc = SMOL_EDEVICE;
+            for (int j = 0; j < nstream; ++j)
+                if (hipStreamSynchronize(streams[j]) != hipSuccess) rc = SMOL_EDEVICE;
             if (rc) break;
             if (hipMemcpyAsync(hctl, dctl, sizeof(IntegCtl) * n_inst, hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess) {
@@ -418,8 +447,13 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
         }
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) rc = SMOL_EDEVICE;
     } while (0);
-    if (ge) (void)hipGraphExecDestroy(ge);
-    if (cap) (void)hipStreamDestroy(cap);
+    for (auto &g : ge)
+        if (g) (void)hipGraphExecDestroy(g);
+    for (auto &st : streams)
+        if (st) {
+            (void)hipStreamSynchronize(st);
+            (void)hipStreamDestroy(st);
+        }
     (void)hipStreamSynchronize(s);
     (void)hipFree(arena);
     if (hctl) (void)hipHostFree(hctl);
