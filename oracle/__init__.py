@@ -39,6 +39,13 @@ class _Opts(ctypes.Structure):
                 ("h_min", ctypes.c_double)]
 
 
+class _PaperOpts(ctypes.Structure):
+    _fields_ = [("scheme", ctypes.c_int32), ("rule", ctypes.c_int32),
+                ("nthreads", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("t_end", ctypes.c_double), ("h0", ctypes.c_double), ("s", ctypes.c_double),
+                ("max_steps", ctypes.c_int64), ("h_min", ctypes.c_double)]
+
+
 class _Stats(ctypes.Structure):
     _fields_ = [("n_rhs", ctypes.c_int64), ("n_accept", ctypes.c_int64),
                 ("n_reject", ctypes.c_int64), ("t", ctypes.c_double),
@@ -59,6 +66,9 @@ def lib():
         L.oracle_integrate.argtypes = [i64, i32, P, P, d, P, ctypes.POINTER(_Opts), P,
                                        ctypes.POINTER(_Stats), P, i64]
         L.oracle_rk_fixed.argtypes = [i64, i32, P, P, d, P, i32, d, i64, i32, P, i32]
+        L.oracle_integrate_paper.argtypes = [i64, i32, P, P, d, P, ctypes.POINTER(_PaperOpts), P,
+                                             ctypes.POINTER(_Stats), P, i64]
+        L.oracle_paper_attempt.argtypes = [i32, i64, i32, P, P, d, P, d, P, P, i32]
         L.oracle_tableau.argtypes = [i32, P, P, P, ctypes.POINTER(i32)]
         L.oracle_moments.argtypes = [i64, P, P]
         L.oracle_moments.restype = None
@@ -136,6 +146,41 @@ def integrate(U, V, lam, n0, t_end, rtol, atol, method=DP54, h0=0.0, max_steps=0
     stats = {f: getattr(st, f) for f, _ in _Stats._fields_}
     nlog = min(log_cap, stats["n_accept"] + stats["n_reject"]) if log_cap else 0
     return out, stats, log[:nlog].copy()
+
+
+# the paper's schemes (Sec. 2) and step-size rules
+RKF45, RK2_DBL, RK4_DBL = 2, 3, 4
+RULE_EQ6, RULE_HALVE_DOUBLE, RULE_FEHLBERG = 0, 1, 2
+
+
+def integrate_paper(U, V, lam, n0, t_end, tol, scheme, rule, h0=0.0, s=0.0, max_steps=0,
+                    h_min=0.0, threads=0, log_cap=0):
+    """The paper's adaptive schemes with the Euclidean error norm.  Returns
+    (n_out, stats, log) with log rows (t_start, h, err/tol, accepted, t_after)."""
+    n0 = _f64(n0)
+    U, V = _factors(U, V, n0.size)
+    o = _PaperOpts(scheme, rule, threads, tol, t_end, h0, s, max_steps, h_min)
+    st = _Stats()
+    out = np.empty_like(n0)
+    log = np.zeros((max(log_cap, 1), 5))
+    lib().oracle_integrate_paper(n0.size, U.shape[0], _p(U), _p(V), float(lam), _p(n0),
+                                 ctypes.byref(o), _p(out), ctypes.byref(st),
+                                 _p(log) if log_cap > 0 else None, log_cap)
+    stats = {f: getattr(st, f) for f, _ in _Stats._fields_}
+    nlog = min(log_cap, stats["n_accept"] + stats["n_reject"]) if log_cap else 0
+    return out, stats, log[:nlog].copy()
+
+
+def paper_attempt(U, V, lam, y, tau, scheme, threads=0):
+    """One attempt of a paper scheme from y: (RKF45: fourth- and fifth-order
+    solutions; doubling: single step and two half steps)."""
+    y = _f64(y)
+    U, V = _factors(U, V, y.size)
+    a, b = np.empty_like(y), np.empty_like(y)
+    rc = lib().oracle_paper_attempt(scheme, y.size, U.shape[0], _p(U), _p(V), float(lam), _p(y),
+                                    float(tau), _p(a), _p(b), threads)
+    assert rc == OK, rc
+    return a, b
 
 
 def rk_fixed(U, V, lam, n0, method, h, nsteps, embedded=False, threads=0):

@@ -34,7 +34,17 @@
  *       sequences; fixed-step convergence orders; the closed form.
  *       The beta (PI) term itself: parity unpinned.
  *   oracle_rk_fixed
- *       Fixed-step version of the same tableaux (order checks).
+ *       Fixed-step version of the same tableaux (order checks), and of
+ *       RKF45 as printed in Sec. 2.
+ *   oracle_integrate_paper
+ *       The paper's own adaptive schemes (Sec. 2): RKF45 with Fehlberg's
+ *       step rule, RK2 / RK4 with step doubling and the step update of
+ *       Eq. (6) or the halve / double rule, Euclidean error norm.
+ *       Pinned by: the K == 1 closed form: local errors of one attempt
+ *       shrink as tau^(p+1) (RK2 p = 2, RK4 p = 4, RKF45's two solutions
+ *       4 and 5) and the two half steps of a doubling attempt are 2^p times
+ *       closer than the single step; whole runs against the closed form at
+ *       several tolerances; the step-size rules' worked examples.
  *   oracle_moments, oracle_features
  *       Moments sum_s s^k n_s and the step-proposer feature vector.
  *   oracle_mlp_forward / oracle_mlp_loss_grad / oracle_adam
@@ -204,10 +214,32 @@ static void tab_dp54(tableau *T)
     T->bh[5] = 187.0 / 2100.0; T->bh[6] = 1.0 / 40.0;
 }
 
+/* Runge--Kutta--Fehlberg 4(5) as printed in Sec. 2 (Fehlberg 1970): six
+ * stages; b = the fourth-order weights the paper propagates, bh = the
+ * fifth-order weights of its error estimate. */
+static void tab_rkf45(tableau *T)
+{
+    memset(T, 0, sizeof(*T));
+    T->stages = 6;
+    T->q = 4;
+    T->a[1][0] = 1.0 / 4.0;
+    T->a[2][0] = 3.0 / 32.0;  T->a[2][1] = 9.0 / 32.0;
+    T->a[3][0] = 1932.0 / 2197.0; T->a[3][1] = -7200.0 / 2197.0; T->a[3][2] = 7296.0 / 2197.0;
+    T->a[4][0] = 439.0 / 216.0; T->a[4][1] = -8.0; T->a[4][2] = 3680.0 / 513.0;
+    T->a[4][3] = -845.0 / 4104.0;
+    T->a[5][0] = -8.0 / 27.0; T->a[5][1] = 2.0; T->a[5][2] = -3544.0 / 2565.0;
+    T->a[5][3] = 1859.0 / 4104.0; T->a[5][4] = -11.0 / 40.0;
+    T->b[0] = 25.0 / 216.0; T->b[2] = 1408.0 / 2565.0; T->b[3] = 2197.0 / 4104.0;
+    T->b[4] = -1.0 / 5.0;
+    T->bh[0] = 16.0 / 135.0; T->bh[2] = 6656.0 / 12825.0; T->bh[3] = 28561.0 / 56430.0;
+    T->bh[4] = -9.0 / 50.0; T->bh[5] = 2.0 / 55.0;
+}
+
 static int get_tableau(int32_t method, tableau *T)
 {
     if (method == 0) { tab_bs32(T); return 0; }
     if (method == 1) { tab_dp54(T); return 0; }
+    if (method == 2) { tab_rkf45(T); return 0; }
     return -1;
 }
 
@@ -449,6 +481,221 @@ int oracle_rk_fixed(int64_t M, int32_t R, const double *U, const double *V,
     memcpy(n_out, y, sizeof(double) * (size_t)M);
     free(buf);
     return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* The paper's adaptive schemes (Sec. 2).                              */
+/* ------------------------------------------------------------------ */
+
+/* scheme: 2 = RKF45 (propagate the fourth-order solution, error
+ *             || n_RK5 - n^{k+1} ||_2), 3 = RK2 with step doubling,
+ *             4 = RK4 with step doubling (one step tau giving n^{k+1}, two
+ *             steps tau/2 giving nhat^{k+1}; error || nhat - n ||_2; the
+ *             two half steps are propagated).
+ * rule:   0 = Eq. (6), tau_new = s tau (tol / err)^(1/p), p the order of the
+ *             scheme (2 for RK2, 4 for RK4 and RKF45);
+ *         1 = halve tau after a rejection, double it after an acceptance;
+ *         2 = Fehlberg's rule: the step scales with the fifth root of
+ *             tol / err, times 0.9 (so err = 2 tol shrinks it by ~20 %,
+ *             err = tol / 2 grows it by ~3 %, err = tol shrinks it by 10 %).
+ * An attempt is accepted iff err <= tol, else repeated from the same state.
+ * Readings where the paper is silent: the factor of rules 0 and 2 is clipped
+ * to [0.2, 10] (err = 0 gives 10); the first step is Hairer's starting step
+ * with the absolute weights sc = tol; the usual step-start clamp and t_end
+ * clip apply.  S(n) at a state is evaluated once and shared by every attempt
+ * and half step that starts there (counted once in n_rhs). */
+typedef struct {
+    int32_t scheme, rule, nthreads;
+    double tol, t_end;
+    double h0;          /* > 0: first step; <= 0: automatic */
+    double s;           /* rule 0 safety factor; <= 0: 1/4 */
+    int64_t max_steps;  /* limit on attempts; <= 0: 10^8 */
+    double h_min;
+} oracle_paper_opts;
+
+static double norm2(const double *x, int64_t M)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < M; ++i) s += x[i] * x[i];
+    return sqrt(s);
+}
+
+/* One RK2 or RK4 step of size tau from y (Sec. 2, as printed: k_i = tau S(.)),
+ * given f0 = S(y); writes y_out.  Returns the number of RHS evaluated. */
+static int classic_step(int32_t scheme, int64_t M, int32_t R, const double *U, const double *V,
+                        double lam, const double *y, const double *f0, double tau,
+                        double *y_out, double *w, int32_t nth)
+{
+    double *k1 = w, *k2 = w + M, *k3 = w + 2 * M, *k4 = w + 3 * M, *z = w + 4 * M;
+    for (int64_t i = 0; i < M; ++i) k1[i] = tau * f0[i];
+    if (scheme == 3) {
+        for (int64_t i = 0; i < M; ++i) z[i] = y[i] + k1[i];
+        oracle_rhs(M, R, U, V, lam, z, k2, nth);
+        for (int64_t i = 0; i < M; ++i) k2[i] *= tau;
+        for (int64_t i = 0; i < M; ++i) y_out[i] = y[i] + (k1[i] + k2[i]) / 2.0;
+        return 1;
+    }
+    for (int64_t i = 0; i < M; ++i) z[i] = y[i] + 0.5 * k1[i];
+    oracle_rhs(M, R, U, V, lam, z, k2, nth);
+    for (int64_t i = 0; i < M; ++i) k2[i] *= tau;
+    for (int64_t i = 0; i < M; ++i) z[i] = y[i] + 0.5 * k2[i];
+    oracle_rhs(M, R, U, V, lam, z, k3, nth);
+    for (int64_t i = 0; i < M; ++i) k3[i] *= tau;
+    for (int64_t i = 0; i < M; ++i) z[i] = y[i] + k3[i];
+    oracle_rhs(M, R, U, V, lam, z, k4, nth);
+    for (int64_t i = 0; i < M; ++i) k4[i] *= tau;
+    for (int64_t i = 0; i < M; ++i)
+        y_out[i] = y[i] + (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]) / 6.0;
+    return 3;
+}
+
+/* One attempt of step tau from y with f0 = S(y): RKF45 writes the fourth-
+ * (y4) and fifth-order (y5) solutions; the doubling schemes write the single
+ * step (y4 <- n^{k+1}) and the two half steps (y5 <- nhat^{k+1}).  The
+ * propagated solution is y4 for RKF45 and y5 for the doubling schemes.
+ * Returns the number of RHS evaluations (S(y) excluded). */
+static int paper_attempt(int32_t scheme, int64_t M, int32_t R, const double *U, const double *V,
+                         double lam, const double *y, const double *f0, double tau, double *y4,
+                         double *y5, double *w, int32_t nth)
+{
+    if (scheme == 2) {
+        tableau T;
+        tab_rkf45(&T);
+        double *K[6], *z = w + 6 * M;
+        for (int j = 0; j < 6; ++j) K[j] = w + (int64_t)j * M;
+        /* k_1 = tau S(n^k), k_2 .. k_6 as printed */
+        for (int64_t s = 0; s < M; ++s) K[0][s] = tau * f0[s];
+        for (int i = 1; i < 6; ++i) {
+            for (int64_t s = 0; s < M; ++s) {
+                double acc = 0.0;
+                for (int j = 0; j < i; ++j) acc += T.a[i][j] * K[j][s];
+                z[s] = y[s] + acc;
+            }
+            oracle_rhs(M, R, U, V, lam, z, K[i], nth);
+            for (int64_t s = 0; s < M; ++s) K[i][s] *= tau;
+        }
+        for (int64_t s = 0; s < M; ++s) {
+            double n4 = y[s], n5 = y[s];
+            for (int j = 0; j < 6; ++j) {
+                n4 += T.b[j] * K[j][s];
+                n5 += T.bh[j] * K[j][s];
+            }
+            y4[s] = n4;
+            y5[s] = n5;
+        }
+        return 5;
+    }
+    /* one step tau, then two steps tau / 2 */
+    double *yh = w + 5 * M, *fh = w + 6 * M;
+    int n = classic_step(scheme, M, R, U, V, lam, y, f0, tau, y4, w, nth);
+    n += classic_step(scheme, M, R, U, V, lam, y, f0, 0.5 * tau, yh, w, nth);
+    oracle_rhs(M, R, U, V, lam, yh, fh, nth);
+    n += 1;
+    n += classic_step(scheme, M, R, U, V, lam, yh, fh, 0.5 * tau, y5, w, nth);
+    return n;
+}
+
+int oracle_paper_attempt(int32_t scheme, int64_t M, int32_t R, const double *U,
+                         const double *V, double lam, const double *y, double tau,
+                         double *y4, double *y5, int32_t nthreads)
+{
+    if (scheme < 2 || scheme > 4 || M < 1) return OR_EINVAL;
+    double *w = (double *)malloc(sizeof(double) * (size_t)M * 8);
+    if (!w) return OR_ENOMEM;
+    oracle_rhs(M, R, U, V, lam, y, w + 7 * M, nthreads);
+    paper_attempt(scheme, M, R, U, V, lam, y, w + 7 * M, tau, y4, y5, w, nthreads);
+    free(w);
+    return OR_OK;
+}
+
+int oracle_integrate_paper(int64_t M, int32_t R, const double *U, const double *V,
+                           double lam, const double *n0, const oracle_paper_opts *o,
+                           double *n_out, oracle_stats *st, double *log, int64_t log_cap)
+{
+    if (M < 1 || R < 1 || !U || !V || !n0 || !o || !n_out || !st) return OR_EINVAL;
+    if (o->scheme < 2 || o->scheme > 4 || o->rule < 0 || o->rule > 2) return OR_EINVAL;
+    if (!(o->tol > 0) || !(o->t_end >= 0) || !isfinite(lam) || lam < 0) return OR_EINVAL;
+    const int p = o->scheme == 3 ? 2 : 4;       /* order of the scheme */
+    const double s_fac = o->s > 0 ? o->s : 0.25;
+    const int64_t max_steps = o->max_steps > 0 ? o->max_steps : 100000000LL;
+    const int32_t nth = o->nthreads;
+    memset(st, 0, sizeof(*st));
+    double *buf = (double *)malloc(sizeof(double) * (size_t)M * 14);
+    if (!buf) return OR_ENOMEM;
+    double *y = buf, *f = buf + M, *yfull = buf + 2 * M;
+    double *yhat = buf + 4 * M, *e = buf + 5 * M, *work = buf + 6 * M;  /* work: 8 M */
+
+    memcpy(y, n0, sizeof(double) * (size_t)M);
+    double t = 0.0, h = 0.0;
+    int64_t attempts = 0, nlog = 0;
+    int status = OR_OK;
+    if (!all_finite(y, M)) { status = OR_ENONFINITE; goto done; }
+    if (o->t_end == 0.0) goto done;
+    oracle_rhs(M, R, U, V, lam, y, f, nth);
+    st->n_rhs = 1;
+    h = o->h0 > 0 ? o->h0
+                  : initial_step(M, R, U, V, lam, y, f, o->t_end, p, 0.0, o->tol, work,
+                                 &st->n_rhs, nth);
+    if (h > o->t_end) h = o->t_end;
+
+    while (t < o->t_end) {
+        double min_step = 10.0 * fabs(nextafter(t, INFINITY) - t);
+        if (o->h_min > min_step) min_step = o->h_min;
+        if (h < min_step) h = min_step;
+        for (;;) {
+            if (attempts >= max_steps) { status = OR_EMAXSTEPS; goto done; }
+            if (h < min_step) { status = OR_ESTEPSIZE; goto done; }
+            double t_new = t + h;
+            if (t_new > o->t_end) t_new = o->t_end;
+            h = t_new - t;
+            st->n_rhs += paper_attempt(o->scheme, M, R, U, V, lam, y, f, h, yfull, yhat, work, nth);
+            double *ynew = o->scheme == 2 ? yfull : yhat;
+            for (int64_t s = 0; s < M; ++s) e[s] = yhat[s] - yfull[s];
+            const double err = norm2(e, M) / o->tol;  /* in units of tol */
+            ++attempts;
+            st->err = err;
+            if (isnan(err) || !all_finite(ynew, M)) {
+                status = OR_ENONFINITE;
+                goto done;
+            }
+            const int accept = err <= 1.0;
+            if (log && nlog < log_cap) {
+                double *row = log + 5 * nlog++;
+                row[0] = t; row[1] = h; row[2] = err; row[3] = accept;
+                row[4] = accept ? t_new : t;
+            }
+            double fac;
+            if (o->rule == 1) {
+                fac = accept ? 2.0 : 0.5;
+            } else {
+                const double ex = o->rule == 2 ? 1.0 / 5.0 : 1.0 / (double)p;
+                const double sf = o->rule == 2 ? 0.9 : s_fac;
+                fac = err == 0.0 ? 10.0 : sf * pow(err, -ex);
+                if (fac > 10.0) fac = 10.0;
+                if (fac < 0.2) fac = 0.2;
+            }
+            if (accept) {
+                t = t_new;
+                h = h * fac;
+                memcpy(y, ynew, sizeof(double) * (size_t)M);
+                st->n_accept += 1;
+                if (t < o->t_end) {
+                    oracle_rhs(M, R, U, V, lam, y, f, nth);
+                    st->n_rhs += 1;
+                }
+                break;
+            }
+            h = h * fac;
+            st->n_reject += 1;
+        }
+    }
+done:
+    st->t = t;
+    st->h = h;
+    st->status = status;
+    memcpy(n_out, y, sizeof(double) * (size_t)M);
+    free(buf);
+    return status;
 }
 
 /* ------------------------------------------------------------------ */
