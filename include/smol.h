@@ -39,14 +39,38 @@ enum {
     SMOL_EUNSUPPORTED = -7 /* valid request this build does not provide */
 };
 
-/* Embedded Runge--Kutta pairs (both first-same-as-last). */
-enum { SMOL_BS32 = 0, SMOL_DP54 = 1 };
+/* Integration schemes.  SMOL_BS32 and SMOL_DP54 are embedded pairs
+ * (first-same-as-last).  The paper's schemes (Sec. 2): SMOL_RKF45 is
+ * Runge--Kutta--Fehlberg 4(5) propagating the fourth-order solution, with
+ * the fifth-order one for the error estimate; SMOL_RK2_DBL is RK2 (Heun)
+ * with step doubling: each attempt takes one step h and two steps h/2,
+ * propagates the latter, and estimates the error by their difference.
+ * Each attempt also evaluates S at its new state, which is the next
+ * attempt's first stage (so a rejected attempt costs one evaluation more
+ * than the scheme itself needs).  SMOL_RK4_DBL (RK4 with step doubling)
+ * needs 12 stage vectors and is not provided: SMOL_EUNSUPPORTED. */
+enum { SMOL_BS32 = 0, SMOL_DP54 = 1, SMOL_RKF45 = 2, SMOL_RK2_DBL = 3, SMOL_RK4_DBL = 4 };
 
 /* Arithmetic of the convolution part of the right-hand side. */
 enum { SMOL_FP64 = 0, SMOL_FP32X2 = 1 };
 
-/* Step-size controller. */
-enum { SMOL_CTRL_PI = 0, SMOL_CTRL_LEARNED = 1 };
+/* Step-size controller.  PI and LEARNED use the weighted-RMS norm below.
+ * The paper's rules (Sec. 2) use the Euclidean norm err = ||e||_2 / tol
+ * with tol = rtol (atol is ignored), accept iff err <= 1, and set the next
+ * step (after acceptance and rejection alike) by
+ *   SMOL_CTRL_FEHLBERG:       h *= 0.9 err^(-1/(q+1))  (q = 4 for RKF45:
+ *                             the fifth root of Fehlberg's rule)
+ *   SMOL_CTRL_STEP_DOUBLING:  h *= s err^(-1/q), Eq. (6), q the scheme's
+ *                             order, s = options.safety (default 1/4)
+ *   SMOL_CTRL_HALVE_DOUBLE:   h *= 2 after acceptance, 1/2 after rejection
+ * with the factor clipped to [0.2, 10] (err = 0 gives 10). */
+enum {
+    SMOL_CTRL_PI = 0,
+    SMOL_CTRL_LEARNED = 1,
+    SMOL_CTRL_FEHLBERG = 2,
+    SMOL_CTRL_STEP_DOUBLING = 3,
+    SMOL_CTRL_HALVE_DOUBLE = 4
+};
 
 typedef struct {
     int64_t n_rhs;     /* right-hand-side evaluations, including the two of
@@ -98,8 +122,8 @@ int smol_rhs(int64_t M, int32_t R, const double *U, const double *V,
  * max(0.2, 0.9 err^(-1/k)).  The first step comes from Hairer's starting
  * procedure; the last one is clipped to land exactly on t_end.
  *
- * n0, n_out: M doubles on the device (n_out may alias n0).  method:
- * SMOL_BS32 or SMOL_DP54.  rtol > 0, atol >= 0, t_end >= 0 (t_end == 0
+ * n0, n_out: M doubles on the device (n_out may alias n0).  method: one of
+ * the schemes above.  rtol > 0, atol >= 0, t_end >= 0 (t_end == 0
  * returns n0 after 0 steps).  stats: HOST pointer, may be NULL.
  * Synchronous: returns after the run with n_out written.  On
  * SMOL_ESTEPSIZE / SMOL_EMAXSTEPS / SMOL_ENONFINITE, n_out holds the last
@@ -118,12 +142,13 @@ typedef struct {
     double alpha, beta; /* PI exponents; alpha <= 0: defaults for both;
                            alpha > 0: both as given (beta = 0 selects the
                            pure I controller) */
-    int32_t controller; /* SMOL_CTRL_PI or SMOL_CTRL_LEARNED */
+    int32_t controller; /* SMOL_CTRL_* */
     int32_t reserved;
     double *log;        /* device pointer or NULL: one row per attempt,
                            (t, h, err, accepted, t_after, M0, M1, M2, M3)
                            as 9 doubles */
     int64_t log_cap;    /* rows available in log */
+    double safety;      /* SMOL_CTRL_STEP_DOUBLING's s; <= 0: 1/4 */
 } smol_options;
 
 /* smol_integrate with options.  The number of log rows written is

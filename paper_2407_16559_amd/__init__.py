@@ -18,9 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libsmol.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTEPSIZE, EMAXSTEPS, ENONFINITE, EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7
-METHODS = {"bs3": 0, "bs32": 0, "dp5": 1, "dp54": 1}
+METHODS = {"bs3": 0, "bs32": 0, "dp5": 1, "dp54": 1, "rkf45": 2, "rk2_dbl": 3, "rk4_dbl": 4}
 PRECISIONS = {"fp64": 0, "fp32x2": 1}
-CONTROLLERS = {"pi": 0, "learned": 1}
+CONTROLLERS = {"pi": 0, "learned": 1, "fehlberg": 2, "step_doubling": 3, "halve_double": 4}
 N_PARAMS = 4865
 
 _lib = None
@@ -47,7 +47,7 @@ class _Options(ctypes.Structure):
                 ("max_steps", ctypes.c_int64), ("alpha", ctypes.c_double),
                 ("beta", ctypes.c_double), ("controller", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("log", ctypes.c_void_p),
-                ("log_cap", ctypes.c_int64)]
+                ("log_cap", ctypes.c_int64), ("safety", ctypes.c_double)]
 
 
 class _Instance(ctypes.Structure):
@@ -155,9 +155,10 @@ def rhs(U, V, lam, n, out=None, precision="fp64"):
 
 
 def _options(h0=0.0, h_min=0.0, max_steps=0, alpha=None, beta=None, controller="pi",
-             log=None):
+             log=None, safety=0.0):
     o = _Options()
     o.h0, o.h_min, o.max_steps = float(h0), float(h_min), int(max_steps)
+    o.safety = float(safety)
     if alpha is not None or beta is not None:
         if alpha is None or beta is None:
             raise ValueError("give both alpha and beta, or neither")

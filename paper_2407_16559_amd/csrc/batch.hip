@@ -145,12 +145,15 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
                                     smol_stats *stats, void *stream)
 {
     if (n_inst < 1 || !inst || !stats) return SMOL_EINVAL;
-    if (method != SMOL_BS32 && method != SMOL_DP54) return SMOL_EINVAL;
+    {
+        const int mrc = check_method(method);
+        if (mrc) return mrc;
+    }
     if (precision != SMOL_FP64 && precision != SMOL_FP32X2) return SMOL_EINVAL;
     smol_options o{};
     if (opts) o = *opts;
     if (o.h0 < 0 || o.h_min < 0 || o.max_steps < 0 || o.log) return SMOL_EINVAL;
-    if (o.controller != SMOL_CTRL_PI && o.controller != SMOL_CTRL_LEARNED) return SMOL_EINVAL;
+    if (!controller_valid(o.controller)) return SMOL_EINVAL;
     for (int i = 0; i < n_inst; ++i) {
         const smol_instance &q = inst[i];
         int rc = check_common(q.M, q.R, q.U, q.V, q.lambda);
@@ -226,7 +229,6 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
         // ---- per-instance device views and control blocks
         IntegCtl *dctl = (IntegCtl *)arena;
         std::vector<IntegDev> hdev(n_inst);
-        const int kq = (method == SMOL_DP54 ? 4 : 2) + 1;
         for (int i = 0; i < n_inst; ++i) {
             const smol_instance &q = inst[i];
             const int logL = br.logL[i];
@@ -266,22 +268,13 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
             c.V = I.Vt;
             c.lam = q.lambda;
             c.t_end = q.t_end;
-            c.rtol = q.rtol;
-            c.atol = q.atol;
             c.h_min = o.h_min;
             c.h0_user = o.h0;
-            c.alpha = o.alpha > 0 ? o.alpha : 0.7 / kq;
-            c.beta = o.alpha > 0 ? o.beta : 0.4 / kq;
-            c.safety = 0.9;
-            c.facmin = 0.2;
-            c.facmax = 10.0;
             c.max_steps = o.max_steps > 0 ? o.max_steps : 100000000LL;
-            c.method = method;
-            c.controller = o.controller;
             c.mlp = o.controller == SMOL_CTRL_LEARNED ? mlp : nullptr;
             c.log = q.log;
             c.log_cap = q.log ? q.log_cap : 0;
-            c.err_prev = 1.0;
+            ctl_setup(c, method, o, q.rtol, q.atol);
             c.done = q.t_end == 0.0;  // nothing to do: n_out = n0
         }
         // ---- tables
@@ -360,7 +353,7 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
                 break;
             }
         if (rc) break;
-        const int S = method == SMOL_DP54 ? 7 : 4;
+        const int S = k_scheme_stages[method];
         auto capture = [&]() -> int {
             for (auto &g : ge)
                 if (g) (void)hipGraphExecDestroy(g);

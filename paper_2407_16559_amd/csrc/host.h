@@ -41,6 +41,48 @@ inline int fft_log2(int64_t M)
     return l < 6 ? 6 : l;
 }
 
+// Stages (with the stage evaluated at the new state) and error-estimate
+// order q of each scheme, indexed by SMOL_BS32 .. SMOL_RK2_DBL.
+static const int k_scheme_stages[4] = {4, 7, 7, 6};
+static const int k_scheme_q[4] = {2, 4, 4, 2};
+
+// SMOL_OK for a scheme this build runs, SMOL_EUNSUPPORTED for a known one it
+// does not, SMOL_EINVAL otherwise.
+inline int check_method(int32_t method)
+{
+    if (method >= SMOL_BS32 && method <= SMOL_RK2_DBL) return SMOL_OK;
+    return method == SMOL_RK4_DBL ? SMOL_EUNSUPPORTED : SMOL_EINVAL;
+}
+inline bool controller_valid(int32_t c) { return c >= SMOL_CTRL_PI && c <= SMOL_CTRL_HALVE_DOUBLE; }
+
+// Control-block settings shared by single and batched runs: tolerances,
+// controller constants and the paper rules' Euclidean norm (sc = tol = rtol).
+inline void ctl_setup(IntegCtl &c, int32_t method, const smol_options &o, double rtol, double atol)
+{
+    const int k = k_scheme_q[method] + 1;
+    c.rtol = rtol;
+    c.atol = atol;
+    if (o.alpha > 0) {
+        c.alpha = o.alpha;
+        c.beta = o.beta;
+    } else {
+        c.alpha = 0.7 / k;
+        c.beta = 0.4 / k;
+    }
+    c.safety = 0.9;
+    c.facmin = 0.2;
+    c.facmax = 10.0;
+    c.method = method;
+    c.controller = o.controller;
+    c.err_prev = 1.0;
+    if (o.controller >= SMOL_CTRL_FEHLBERG) {
+        c.l2 = 1;
+        c.rtol = 0.0;
+        c.atol = rtol;
+        c.paper_s = o.safety > 0 ? o.safety : 0.25;
+    }
+}
+
 // serialises plan / table creation and use across host threads
 extern SMOL_HIDDEN std::mutex g_mu;
 SMOL_HIDDEN int get_roots(int dev, DevRoots **out);

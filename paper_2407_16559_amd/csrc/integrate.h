@@ -20,7 +20,11 @@
 #define ST_ESTEPSIZE (-4)
 #define ST_EMAXSTEPS (-5)
 #define ST_ENONFINITE (-6)
-#define CTRL_LEARNED 1  // SMOL_CTRL_LEARNED
+// Controllers, mirrored from smol.h.
+#define CTRL_LEARNED 1        // SMOL_CTRL_LEARNED
+#define CTRL_FEHLBERG 2       // SMOL_CTRL_FEHLBERG
+#define CTRL_EQ6 3            // SMOL_CTRL_STEP_DOUBLING
+#define CTRL_HALVE_DOUBLE 4   // SMOL_CTRL_HALVE_DOUBLE
 
 struct Tableau {
     int S;             // stages including the FSAL stage
@@ -29,8 +33,17 @@ struct Tableau {
     double d[8];       // b_j - bhat_j
 };
 
-// Bogacki & Shampine (1989) 3(2) and Dormand & Prince (1980) 5(4).
-__constant__ Tableau c_tab[2] = {
+// Bogacki & Shampine (1989) 3(2), Dormand & Prince (1980) 5(4), and two of
+// the paper's schemes (Sec. 2) written as tableaux whose last stage is
+// evaluated at the propagated solution, so that they run on the same stage
+// machinery:
+//   RKF45 (Fehlberg 1970), propagating the fourth-order solution: stages 1-6
+//   as printed, stage 7 = S(n^{k+1}) (the next step's k_1); d = b4 - b5.
+//   RK2 with step doubling: stage 2 is the single step's second stage
+//   (n + h k1), stages 3-5 the two half steps (n + h/2 k1; the midpoint
+//   n + h/4 (k1 + k3); its half step n + h (k1/4 + k3/4 + k4/2)), stage 6 the
+//   two-half-step solution nhat (propagated); d = nhat - single step.
+__constant__ Tableau c_tab[4] = {
     {4, 2,
      {{0}, {1.0 / 2}, {0.0, 3.0 / 4}, {2.0 / 9, 1.0 / 3, 4.0 / 9}},
      {2.0 / 9 - 7.0 / 24, 1.0 / 3 - 1.0 / 4, 4.0 / 9 - 1.0 / 3, -1.0 / 8}},
@@ -44,6 +57,24 @@ __constant__ Tableau c_tab[2] = {
       {35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}},
      {35.0 / 384 - 5179.0 / 57600, 0.0, 500.0 / 1113 - 7571.0 / 16695, 125.0 / 192 - 393.0 / 640,
       -2187.0 / 6784 + 92097.0 / 339200, 11.0 / 84 - 187.0 / 2100, -1.0 / 40}},
+    {7, 4,
+     {{0},
+      {1.0 / 4},
+      {3.0 / 32, 9.0 / 32},
+      {1932.0 / 2197, -7200.0 / 2197, 7296.0 / 2197},
+      {439.0 / 216, -8.0, 3680.0 / 513, -845.0 / 4104},
+      {-8.0 / 27, 2.0, -3544.0 / 2565, 1859.0 / 4104, -11.0 / 40},
+      {25.0 / 216, 0.0, 1408.0 / 2565, 2197.0 / 4104, -1.0 / 5, 0.0}},
+     {25.0 / 216 - 16.0 / 135, 0.0, 1408.0 / 2565 - 6656.0 / 12825,
+      2197.0 / 4104 - 28561.0 / 56430, -1.0 / 5 + 9.0 / 50, -2.0 / 55, 0.0}},
+    {6, 2,
+     {{0},
+      {1.0},
+      {1.0 / 2, 0.0},
+      {1.0 / 4, 0.0, 1.0 / 4},
+      {1.0 / 4, 0.0, 1.0 / 4, 1.0 / 2},
+      {1.0 / 4, 0.0, 1.0 / 4, 1.0 / 4, 1.0 / 4}},
+     {1.0 / 4 - 1.0 / 2, -1.0 / 2, 1.0 / 4, 1.0 / 4, 1.0 / 4, 0.0}},
 };
 
 struct IntegCtl {
@@ -62,7 +93,22 @@ struct IntegCtl {
     int32_t status, done, cur, kp, rejected, n_fallback;
     double err_hist[4];
     int32_t n_hist, use_pi;
+    // the paper's controllers: Euclidean error norm (sc = tol), Eq. (6) safety
+    int32_t l2;
+    double paper_s;
 };
+
+// Step factor of the paper's rules (Sec. 2): Fehlberg's fifth-root rule
+// with 0.9, Eq. (6) s (tol/err)^(1/p), or halving / doubling; clipped to
+// [facmin, facmax], err = 0 giving facmax.
+__device__ inline double paper_factor(const IntegCtl &c, int q, double err, bool accept)
+{
+    if (c.controller == CTRL_HALVE_DOUBLE) return accept ? 2.0 : 0.5;
+    const bool fehl = c.controller == CTRL_FEHLBERG;
+    const double ex = fehl ? 1.0 / (double)(q + 1) : 1.0 / (double)q;
+    double fac = err == 0.0 ? c.facmax : (fehl ? 0.9 : c.paper_s) * pow(err, -ex);
+    return fmin(fmax(fac, c.facmin), c.facmax);
+}
 
 struct IntegDev {
     int64_t M, Mt;
@@ -344,7 +390,7 @@ __device__ inline void controller_step(const IntegDev &I, int njobs)
     block_sum_epart(I.epart, njobs, tot);
     const Tableau &T = c_tab[c.method];
     const int k = T.q + 1;
-    const double err = rms_of(tot[0], I.M);
+    const double err = c.l2 ? sqrt(tot[0]) : rms_of(tot[0], I.M);
     const bool accept = err <= 1.0;
     const bool bad = isnan(err) || tot[5] > 0.0;
     // error history including this attempt (most recent first)
@@ -389,9 +435,12 @@ __device__ inline void controller_step(const IntegDev &I, int njobs)
         c.done = 1;
         return;
     }
+    const bool paper = c.controller >= CTRL_FEHLBERG;
     if (accept) {
         double fac;
-        if (learned) {
+        if (paper) {
+            fac = paper_factor(c, T.q, err, true);
+        } else if (learned) {
             fac = exp(dlog);
         } else {
             if (c.controller == CTRL_LEARNED) c.n_fallback += 1;
@@ -417,8 +466,13 @@ __device__ inline void controller_step(const IntegDev &I, int njobs)
         }
         prepare_attempt(c, true);
     } else {
-        double fac = c.safety * pow(err, -1.0 / (double)k);
-        if (fac < c.facmin) fac = c.facmin;
+        double fac;
+        if (paper) {
+            fac = paper_factor(c, T.q, err, false);
+        } else {
+            fac = c.safety * pow(err, -1.0 / (double)k);
+            if (fac < c.facmin) fac = c.facmin;
+        }
         c.h = c.h * fac;
         c.rejected = 1;
         c.n_reject += 1;

@@ -293,7 +293,7 @@ extern "C" int smol_proposer_dataset(const double *log, int64_t rows, int32_t me
 {
     if (!log || !X || !target || !n_out || rows < 0 || rows > (1LL << 30)) return SMOL_EINVAL;
     if (!(err_target > 0.0) || !(err_target <= 1.0)) return SMOL_EINVAL;
-    if (method != SMOL_BS32 && method != SMOL_DP54) return SMOL_EINVAL;
+    if (check_method(method)) return SMOL_EINVAL;
     *n_out = 0;
     if (rows < 2) return SMOL_OK;
     hipStream_t s = (hipStream_t)stream;
@@ -321,7 +321,7 @@ extern "C" int smol_proposer_dataset(const double *log, int64_t rows, int32_t me
         }
         *n_out = o;
         if (hipMemcpyAsync(off, ho.data(), sizeof(int64_t) * nb, hipMemcpyHostToDevice, s)) rc = SMOL_EDEVICE;
-        const int k = (method == SMOL_DP54 ? 4 : 2) + 1;
+        const int k = k_scheme_q[method] + 1;
         hipLaunchKernelGGL(k_dataset_rows, dim3(nb), dim3(SMOL_WG), 0, s, log, rows, k, err_target,
                            flag, off, X, target);
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s)) rc = SMOL_EDEVICE;

@@ -66,7 +66,7 @@ struct Plan {
     IntegCtl *ctl = nullptr;       // device control block
     IntegCtl *host = nullptr;      // pinned mirror
     hipStream_t cap = nullptr;     // capture stream
-    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};  // per scheme
     // launch schedule: variant of kernels A, B, C and their grids
     int var[3] = {0, 0, 0};
     PhaseDims dA{}, dB{}, dC{}, dCf{};
@@ -302,7 +302,7 @@ int get_step_graph(Plan *p, const IntegDev &I, int method, hipGraphExec_t *out)
         *out = p->graph[method];
         return SMOL_OK;
     }
-    const int S = method == SMOL_DP54 ? 7 : 4;
+    const int S = k_scheme_stages[method];
     hipGraph_t g;
     HIP_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
     int rc = SMOL_OK;
@@ -415,13 +415,13 @@ extern "C" int smol_integrate_ex(int64_t M, int32_t R, const double *U, const do
     int rc = check_common(M, R, U, V, lambda);
     if (rc) return rc;
     if (!n0 || !n_out) return SMOL_EINVAL;
-    if (method != SMOL_BS32 && method != SMOL_DP54) return SMOL_EINVAL;
+    if ((rc = check_method(method))) return rc;
     if (precision != SMOL_FP64 && precision != SMOL_FP32X2) return SMOL_EINVAL;
     if (!(rtol > 0) || !(atol >= 0) || !(t_end >= 0) || !std::isfinite(t_end)) return SMOL_EINVAL;
     smol_options o{};
     if (opts) o = *opts;
     if (o.h0 < 0 || o.h_min < 0 || o.max_steps < 0 || (o.log && o.log_cap < 0)) return SMOL_EINVAL;
-    if (o.controller != SMOL_CTRL_PI && o.controller != SMOL_CTRL_LEARNED) return SMOL_EINVAL;
+    if (!controller_valid(o.controller)) return SMOL_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     if (stats) memset(stats, 0, sizeof(*stats));
     if (t_end == 0.0) {
@@ -436,35 +436,18 @@ extern "C" int smol_integrate_ex(int64_t M, int32_t R, const double *U, const do
     if ((rc = get_roots(p->dev, &r))) return rc;
     if ((rc = alloc_integ(p))) return rc;
     const IntegDev I = integ_dev(p, r);
-    const Tableau *Tdummy = nullptr;
-    (void)Tdummy;
-    const int k = (method == SMOL_DP54 ? 4 : 2) + 1;
     IntegCtl &c = *p->host;
     memset(&c, 0, sizeof(c));
     c.U = I.Ut;
     c.V = I.Vt;
     c.lam = lambda;
     c.t_end = t_end;
-    c.rtol = rtol;
-    c.atol = atol;
     c.h_min = o.h_min;
     c.h0_user = o.h0;
-    if (o.alpha > 0) {
-        c.alpha = o.alpha;
-        c.beta = o.beta;
-    } else {
-        c.alpha = 0.7 / k;
-        c.beta = 0.4 / k;
-    }
-    c.safety = 0.9;
-    c.facmin = 0.2;
-    c.facmax = 10.0;
     c.max_steps = o.max_steps > 0 ? o.max_steps : 100000000LL;
     c.log = o.log;
     c.log_cap = o.log ? o.log_cap : 0;
-    c.method = method;
-    c.controller = o.controller;
-    c.err_prev = 1.0;
+    ctl_setup(c, method, o, rtol, atol);
     if (o.controller == SMOL_CTRL_LEARNED) {
         c.mlp = proposer_weights(p->dev);
         if (!c.mlp) return SMOL_EINVAL;  // smol_proposer_set first
@@ -643,7 +626,7 @@ extern "C" int smol_autotune(int64_t M, int32_t R, const double *U, const double
     int rc = check_common(M, R, U, V, lambda);
     if (rc) return rc;
     if (!n0 || !variants_out || attempts < 1 || reps < 1) return SMOL_EINVAL;
-    if (method != SMOL_BS32 && method != SMOL_DP54) return SMOL_EINVAL;
+    if ((rc = check_method(method))) return rc;
     const int logL = fft_log2(M);
     double *scratch = nullptr;
     HIP_TRY(hipMalloc(&scratch, sizeof(double) * (size_t)M));
