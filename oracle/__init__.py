@@ -36,14 +36,15 @@ class _Opts(ctypes.Structure):
                 ("max_steps", ctypes.c_int64), ("alpha", ctypes.c_double),
                 ("beta", ctypes.c_double), ("safety", ctypes.c_double),
                 ("facmin", ctypes.c_double), ("facmax", ctypes.c_double),
-                ("h_min", ctypes.c_double)]
+                ("h_min", ctypes.c_double), ("source", ctypes.c_void_p)]
 
 
 class _PaperOpts(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int32), ("rule", ctypes.c_int32),
                 ("nthreads", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("t_end", ctypes.c_double), ("h0", ctypes.c_double), ("s", ctypes.c_double),
-                ("max_steps", ctypes.c_int64), ("h_min", ctypes.c_double)]
+                ("max_steps", ctypes.c_int64), ("h_min", ctypes.c_double),
+                ("source", ctypes.c_void_p)]
 
 
 class _Stats(ctypes.Structure):
@@ -62,6 +63,7 @@ def lib():
         P = ctypes.POINTER(ctypes.c_double)
         i64, i32, d = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         L.oracle_rhs.argtypes = [i64, i32, P, P, d, P, P, i32]
+        L.oracle_rhs_source.argtypes = [i64, i32, P, P, d, P, P, P, i32]
         L.oracle_rhs_entries.argtypes = [i64, i32, P, P, d, P, ctypes.POINTER(i64), i64, P, i32]
         L.oracle_integrate.argtypes = [i64, i32, P, P, d, P, ctypes.POINTER(_Opts), P,
                                        ctypes.POINTER(_Stats), P, i64]
@@ -130,13 +132,15 @@ def rhs_entries(U, V, lam, n, idx, threads=0):
 
 def integrate(U, V, lam, n0, t_end, rtol, atol, method=DP54, h0=0.0, max_steps=0,
               alpha=0.0, beta=-1.0, safety=0.0, facmin=0.0, facmax=0.0, threads=0,
-              log_cap=0, h_min=0.0):
-    """Adaptive embedded RK integration.  Returns (n_out, stats, log) where log
-    rows are (t_start, h, err, accepted, t_after) per step attempt."""
+              log_cap=0, h_min=0.0, source=None):
+    """Adaptive embedded RK integration (optional Eq. (3) sources).  Returns
+    (n_out, stats, log) where log rows are (t_start, h, err, accepted,
+    t_after) per step attempt."""
     n0 = _f64(n0)
     U, V = _factors(U, V, n0.size)
+    src = None if source is None else _f64(source)
     o = _Opts(method, threads, rtol, atol, t_end, h0, max_steps, alpha, beta, safety,
-              facmin, facmax, h_min)
+              facmin, facmax, h_min, None if src is None else src.ctypes.data)
     st = _Stats()
     out = np.empty_like(n0)
     log = np.zeros((max(log_cap, 1), 5))
@@ -153,13 +157,27 @@ RKF45, RK2_DBL, RK4_DBL = 2, 3, 4
 RULE_EQ6, RULE_HALVE_DOUBLE, RULE_FEHLBERG = 0, 1, 2
 
 
+def rhs_source(U, V, lam, n, source, threads=0):
+    """Eq. (3): S(n) + P (constant sources)."""
+    n = _f64(n)
+    U, V = _factors(U, V, n.size)
+    src = _f64(source)
+    out = np.empty_like(n)
+    rc = lib().oracle_rhs_source(n.size, U.shape[0], _p(U), _p(V), float(lam), _p(n), _p(src),
+                                 _p(out), threads)
+    assert rc == OK, rc
+    return out
+
+
 def integrate_paper(U, V, lam, n0, t_end, tol, scheme, rule, h0=0.0, s=0.0, max_steps=0,
-                    h_min=0.0, threads=0, log_cap=0):
+                    h_min=0.0, threads=0, log_cap=0, source=None):
     """The paper's adaptive schemes with the Euclidean error norm.  Returns
     (n_out, stats, log) with log rows (t_start, h, err/tol, accepted, t_after)."""
     n0 = _f64(n0)
     U, V = _factors(U, V, n0.size)
-    o = _PaperOpts(scheme, rule, threads, tol, t_end, h0, s, max_steps, h_min)
+    src = None if source is None else _f64(source)
+    o = _PaperOpts(scheme, rule, threads, tol, t_end, h0, s, max_steps, h_min,
+                   None if src is None else src.ctypes.data)
     st = _Stats()
     out = np.empty_like(n0)
     log = np.zeros((max(log_cap, 1), 5))

@@ -36,6 +36,12 @@
  *   oracle_rk_fixed
  *       Fixed-step version of the same tableaux (order checks), and of
  *       RKF45 as printed in Sec. 2.
+ *   oracle_rhs_source
+ *       Eq. (3): the right-hand side plus constant sources P_s (also a
+ *       field of both integrators' options).  Pinned by: K == 0 gives
+ *       n(t) = n0 + P t; the K == 1 number density with a monomer source
+ *       obeys N' = P_1 - N^2 / 2 (closed form); the mass balance
+ *       sum s S_s = sum s P_s - F_trunc.
  *   oracle_integrate_paper
  *       The paper's own adaptive schemes (Sec. 2): RKF45 with Fehlberg's
  *       step rule, RK2 / RK4 with step doubling and the step update of
@@ -146,6 +152,24 @@ int oracle_rhs(int64_t M, int32_t R, const double *U, const double *V,
 }
 
 /* S at selected 0-based indices idx[0..nidx) (index s-1 holds size s). */
+/* Eq. (3): the same right-hand side plus constant sources P_s (src may be
+ * NULL: no sources).  The printed P_k is read as P_s. */
+static void rhs_src(int64_t M, int32_t R, const double *U, const double *V, double lam,
+                    const double *src, const double *n, double *out, int32_t nth)
+{
+    oracle_rhs(M, R, U, V, lam, n, out, nth);
+    if (src)
+        for (int64_t s = 0; s < M; ++s) out[s] += src[s];
+}
+
+int oracle_rhs_source(int64_t M, int32_t R, const double *U, const double *V, double lam,
+                      const double *n, const double *src, double *out, int32_t nthreads)
+{
+    if (M < 1 || R < 1 || !U || !V || !n || !out) return OR_EINVAL;
+    rhs_src(M, R, U, V, lam, src, n, out, nthreads);
+    return OR_OK;
+}
+
 int oracle_rhs_entries(int64_t M, int32_t R, const double *U, const double *V,
                        double lam, const double *n, const int64_t *idx,
                        int64_t nidx, double *out, int32_t nthreads)
@@ -271,6 +295,7 @@ typedef struct {
     double alpha, beta; /* PI exponents; alpha <= 0: 0.7/k, beta < 0: 0.4/k */
     double safety, facmin, facmax; /* <= 0: 0.9, 0.2, 10 */
     double h_min;       /* smallest allowed step (besides 10 ulps of t) */
+    const double *source; /* Eq. (3) sources P_s (M doubles) or NULL */
 } oracle_opts;
 
 typedef struct {
@@ -296,7 +321,7 @@ static int all_finite(const double *x, int64_t M)
 /* Starting step of Hairer, Norsett & Wanner, Solving ODEs I, Sec. II.4,
  * with q the order of the embedded solution (exponent 1/(q+1)). */
 static double initial_step(int64_t M, int32_t R, const double *U,
-                           const double *V, double lam, const double *y0,
+                           const double *V, double lam, const double *src, const double *y0,
                            const double *f0, double t_span, int q,
                            double rtol, double atol, double *work,
                            int64_t *n_rhs, int32_t nth)
@@ -310,7 +335,7 @@ static double initial_step(int64_t M, int32_t R, const double *U,
     double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
     if (h0 > t_span) h0 = t_span;
     for (int64_t i = 0; i < M; ++i) y1[i] = y0[i] + h0 * f0[i];
-    oracle_rhs(M, R, U, V, lam, y1, f1, nth);
+    rhs_src(M, R, U, V, lam, src, y1, f1, nth);
     *n_rhs += 1;
     for (int64_t i = 0; i < M; ++i) tmp[i] = (f1[i] - f0[i]) / sc[i];
     double d2 = rms(tmp, M) / h0;
@@ -344,6 +369,7 @@ int oracle_integrate(int64_t M, int32_t R, const double *U, const double *V,
     const double facmax = o->facmax > 0 ? o->facmax : 10.0;
     const int64_t max_steps = o->max_steps > 0 ? o->max_steps : 100000000LL;
     const int32_t nth = o->nthreads;
+    const double *src = o->source;
 
     memset(st, 0, sizeof(*st));
     double *buf = (double *)malloc(sizeof(double) * (size_t)M * (size_t)(S + 7));
@@ -359,10 +385,10 @@ int oracle_integrate(int64_t M, int32_t R, const double *U, const double *V,
     if (!all_finite(y, M)) { status = OR_ENONFINITE; goto done; }
     if (o->t_end == 0.0) goto done;
 
-    oracle_rhs(M, R, U, V, lam, y, K[0], nth);
+    rhs_src(M, R, U, V, lam, src, y, K[0], nth);
     st->n_rhs = 1;
     h = o->h0 > 0 ? o->h0
-                  : initial_step(M, R, U, V, lam, y, K[0], o->t_end, T.q,
+                  : initial_step(M, R, U, V, lam, src, y, K[0], o->t_end, T.q,
                                  o->rtol, o->atol, work, &st->n_rhs, nth);
     if (h > o->t_end) h = o->t_end;
 
@@ -385,7 +411,7 @@ int oracle_integrate(int64_t M, int32_t R, const double *U, const double *V,
                     for (int j = 0; j < i; ++j) acc += T.a[i][j] * K[j][s];
                     dst[s] = y[s] + h * acc;
                 }
-                oracle_rhs(M, R, U, V, lam, dst, K[i], nth);
+                rhs_src(M, R, U, V, lam, src, dst, K[i], nth);
                 st->n_rhs += 1;
             }
             /* the last stage of both pairs is the propagated solution (FSAL) */
@@ -456,6 +482,7 @@ int oracle_rk_fixed(int64_t M, int32_t R, const double *U, const double *V,
     tableau T;
     if (get_tableau(method, &T) || M < 1 || nsteps < 0) return OR_EINVAL;
     const int S = T.stages;
+    const double *src = NULL;
     double *buf = (double *)malloc(sizeof(double) * (size_t)M * (size_t)(S + 2));
     if (!buf) return OR_ENOMEM;
     double *y = buf, *ytmp = buf + M, *K[MAXST];
@@ -463,14 +490,14 @@ int oracle_rk_fixed(int64_t M, int32_t R, const double *U, const double *V,
     memcpy(y, n0, sizeof(double) * (size_t)M);
     const double *w = use_embedded ? T.bh : T.b;
     for (int64_t step = 0; step < nsteps; ++step) {
-        oracle_rhs(M, R, U, V, lam, y, K[0], nthreads);
+        rhs_src(M, R, U, V, lam, src, y, K[0], nthreads);
         for (int i = 1; i < S; ++i) {
             for (int64_t s = 0; s < M; ++s) {
                 double acc = 0.0;
                 for (int j = 0; j < i; ++j) acc += T.a[i][j] * K[j][s];
                 ytmp[s] = y[s] + h * acc;
             }
-            oracle_rhs(M, R, U, V, lam, ytmp, K[i], nthreads);
+            rhs_src(M, R, U, V, lam, src, ytmp, K[i], nthreads);
         }
         for (int64_t s = 0; s < M; ++s) {
             double acc = 0.0;
@@ -511,6 +538,7 @@ typedef struct {
     double s;           /* rule 0 safety factor; <= 0: 1/4 */
     int64_t max_steps;  /* limit on attempts; <= 0: 10^8 */
     double h_min;
+    const double *source; /* Eq. (3) sources P_s (M doubles) or NULL */
 } oracle_paper_opts;
 
 static double norm2(const double *x, int64_t M)
@@ -523,26 +551,26 @@ static double norm2(const double *x, int64_t M)
 /* One RK2 or RK4 step of size tau from y (Sec. 2, as printed: k_i = tau S(.)),
  * given f0 = S(y); writes y_out.  Returns the number of RHS evaluated. */
 static int classic_step(int32_t scheme, int64_t M, int32_t R, const double *U, const double *V,
-                        double lam, const double *y, const double *f0, double tau,
+                        double lam, const double *src, const double *y, const double *f0, double tau,
                         double *y_out, double *w, int32_t nth)
 {
     double *k1 = w, *k2 = w + M, *k3 = w + 2 * M, *k4 = w + 3 * M, *z = w + 4 * M;
     for (int64_t i = 0; i < M; ++i) k1[i] = tau * f0[i];
     if (scheme == 3) {
         for (int64_t i = 0; i < M; ++i) z[i] = y[i] + k1[i];
-        oracle_rhs(M, R, U, V, lam, z, k2, nth);
+        rhs_src(M, R, U, V, lam, src, z, k2, nth);
         for (int64_t i = 0; i < M; ++i) k2[i] *= tau;
         for (int64_t i = 0; i < M; ++i) y_out[i] = y[i] + (k1[i] + k2[i]) / 2.0;
         return 1;
     }
     for (int64_t i = 0; i < M; ++i) z[i] = y[i] + 0.5 * k1[i];
-    oracle_rhs(M, R, U, V, lam, z, k2, nth);
+    rhs_src(M, R, U, V, lam, src, z, k2, nth);
     for (int64_t i = 0; i < M; ++i) k2[i] *= tau;
     for (int64_t i = 0; i < M; ++i) z[i] = y[i] + 0.5 * k2[i];
-    oracle_rhs(M, R, U, V, lam, z, k3, nth);
+    rhs_src(M, R, U, V, lam, src, z, k3, nth);
     for (int64_t i = 0; i < M; ++i) k3[i] *= tau;
     for (int64_t i = 0; i < M; ++i) z[i] = y[i] + k3[i];
-    oracle_rhs(M, R, U, V, lam, z, k4, nth);
+    rhs_src(M, R, U, V, lam, src, z, k4, nth);
     for (int64_t i = 0; i < M; ++i) k4[i] *= tau;
     for (int64_t i = 0; i < M; ++i)
         y_out[i] = y[i] + (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]) / 6.0;
@@ -555,7 +583,7 @@ static int classic_step(int32_t scheme, int64_t M, int32_t R, const double *U, c
  * propagated solution is y4 for RKF45 and y5 for the doubling schemes.
  * Returns the number of RHS evaluations (S(y) excluded). */
 static int paper_attempt(int32_t scheme, int64_t M, int32_t R, const double *U, const double *V,
-                         double lam, const double *y, const double *f0, double tau, double *y4,
+                         double lam, const double *src, const double *y, const double *f0, double tau, double *y4,
                          double *y5, double *w, int32_t nth)
 {
     if (scheme == 2) {
@@ -571,7 +599,7 @@ static int paper_attempt(int32_t scheme, int64_t M, int32_t R, const double *U, 
                 for (int j = 0; j < i; ++j) acc += T.a[i][j] * K[j][s];
                 z[s] = y[s] + acc;
             }
-            oracle_rhs(M, R, U, V, lam, z, K[i], nth);
+            rhs_src(M, R, U, V, lam, src, z, K[i], nth);
             for (int64_t s = 0; s < M; ++s) K[i][s] *= tau;
         }
         for (int64_t s = 0; s < M; ++s) {
@@ -587,11 +615,11 @@ static int paper_attempt(int32_t scheme, int64_t M, int32_t R, const double *U, 
     }
     /* one step tau, then two steps tau / 2 */
     double *yh = w + 5 * M, *fh = w + 6 * M;
-    int n = classic_step(scheme, M, R, U, V, lam, y, f0, tau, y4, w, nth);
-    n += classic_step(scheme, M, R, U, V, lam, y, f0, 0.5 * tau, yh, w, nth);
-    oracle_rhs(M, R, U, V, lam, yh, fh, nth);
+    int n = classic_step(scheme, M, R, U, V, lam, src, y, f0, tau, y4, w, nth);
+    n += classic_step(scheme, M, R, U, V, lam, src, y, f0, 0.5 * tau, yh, w, nth);
+    rhs_src(M, R, U, V, lam, src, yh, fh, nth);
     n += 1;
-    n += classic_step(scheme, M, R, U, V, lam, yh, fh, 0.5 * tau, y5, w, nth);
+    n += classic_step(scheme, M, R, U, V, lam, src, yh, fh, 0.5 * tau, y5, w, nth);
     return n;
 }
 
@@ -600,10 +628,11 @@ int oracle_paper_attempt(int32_t scheme, int64_t M, int32_t R, const double *U,
                          double *y4, double *y5, int32_t nthreads)
 {
     if (scheme < 2 || scheme > 4 || M < 1) return OR_EINVAL;
+    const double *src = NULL;
     double *w = (double *)malloc(sizeof(double) * (size_t)M * 8);
     if (!w) return OR_ENOMEM;
-    oracle_rhs(M, R, U, V, lam, y, w + 7 * M, nthreads);
-    paper_attempt(scheme, M, R, U, V, lam, y, w + 7 * M, tau, y4, y5, w, nthreads);
+    rhs_src(M, R, U, V, lam, src, y, w + 7 * M, nthreads);
+    paper_attempt(scheme, M, R, U, V, lam, src, y, w + 7 * M, tau, y4, y5, w, nthreads);
     free(w);
     return OR_OK;
 }
@@ -619,6 +648,7 @@ int oracle_integrate_paper(int64_t M, int32_t R, const double *U, const double *
     const double s_fac = o->s > 0 ? o->s : 0.25;
     const int64_t max_steps = o->max_steps > 0 ? o->max_steps : 100000000LL;
     const int32_t nth = o->nthreads;
+    const double *src = o->source;
     memset(st, 0, sizeof(*st));
     double *buf = (double *)malloc(sizeof(double) * (size_t)M * 14);
     if (!buf) return OR_ENOMEM;
@@ -631,10 +661,10 @@ int oracle_integrate_paper(int64_t M, int32_t R, const double *U, const double *
     int status = OR_OK;
     if (!all_finite(y, M)) { status = OR_ENONFINITE; goto done; }
     if (o->t_end == 0.0) goto done;
-    oracle_rhs(M, R, U, V, lam, y, f, nth);
+    rhs_src(M, R, U, V, lam, src, y, f, nth);
     st->n_rhs = 1;
     h = o->h0 > 0 ? o->h0
-                  : initial_step(M, R, U, V, lam, y, f, o->t_end, p, 0.0, o->tol, work,
+                  : initial_step(M, R, U, V, lam, src, y, f, o->t_end, p, 0.0, o->tol, work,
                                  &st->n_rhs, nth);
     if (h > o->t_end) h = o->t_end;
 
@@ -648,7 +678,7 @@ int oracle_integrate_paper(int64_t M, int32_t R, const double *U, const double *
             double t_new = t + h;
             if (t_new > o->t_end) t_new = o->t_end;
             h = t_new - t;
-            st->n_rhs += paper_attempt(o->scheme, M, R, U, V, lam, y, f, h, yfull, yhat, work, nth);
+            st->n_rhs += paper_attempt(o->scheme, M, R, U, V, lam, src, y, f, h, yfull, yhat, work, nth);
             double *ynew = o->scheme == 2 ? yfull : yhat;
             for (int64_t s = 0; s < M; ++s) e[s] = yhat[s] - yfull[s];
             const double err = norm2(e, M) / o->tol;  /* in units of tol */
@@ -680,7 +710,7 @@ int oracle_integrate_paper(int64_t M, int32_t R, const double *U, const double *
                 memcpy(y, ynew, sizeof(double) * (size_t)M);
                 st->n_accept += 1;
                 if (t < o->t_end) {
-                    oracle_rhs(M, R, U, V, lam, y, f, nth);
+                    rhs_src(M, R, U, V, lam, src, y, f, nth);
                     st->n_rhs += 1;
                 }
                 break;
