@@ -109,6 +109,13 @@ int smol_rhs(int64_t M, int32_t R, const double *U, const double *V,
              double lambda, const double *n, double *dndt, int32_t precision,
              void *stream);
 
+/* smol_rhs plus constant sources (Eq. (3), the printed P_k read as P_s):
+ * dndt = S(n) + source.  source: M doubles on the device, or NULL (no
+ * sources); must not alias dndt.  Otherwise as smol_rhs. */
+int smol_rhs_ex(int64_t M, int32_t R, const double *U, const double *V,
+                double lambda, const double *n, const double *source,
+                double *dndt, int32_t precision, void *stream);
+
 /*
  * smol_integrate -- integrate dn/dt = S(n), n(0) = n0 (Sec. 2, Eq. (5)) to
  * t_end with an embedded explicit Runge--Kutta pair and adaptive steps
@@ -149,6 +156,9 @@ typedef struct {
                            as 9 doubles */
     int64_t log_cap;    /* rows available in log */
     double safety;      /* SMOL_CTRL_STEP_DOUBLING's s; <= 0: 1/4 */
+    const double *source; /* constant sources P_s of Eq. (3): M doubles on
+                           the device, or NULL (the right-hand side is then
+                           S(n) + source throughout the run) */
 } smol_options;
 
 /* smol_integrate with options.  The number of log rows written is
@@ -172,6 +182,7 @@ typedef struct {
     double t_end, rtol, atol;
     double *log;
     int64_t log_cap;
+    const double *source;  /* Eq. (3) sources (M doubles) or NULL */
 } smol_instance;
 
 /*

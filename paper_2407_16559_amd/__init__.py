@@ -47,7 +47,8 @@ class _Options(ctypes.Structure):
                 ("max_steps", ctypes.c_int64), ("alpha", ctypes.c_double),
                 ("beta", ctypes.c_double), ("controller", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("log", ctypes.c_void_p),
-                ("log_cap", ctypes.c_int64), ("safety", ctypes.c_double)]
+                ("log_cap", ctypes.c_int64), ("safety", ctypes.c_double),
+                ("source", ctypes.c_void_p)]
 
 
 class _Instance(ctypes.Structure):
@@ -55,7 +56,8 @@ class _Instance(ctypes.Structure):
                 ("U", ctypes.c_void_p), ("V", ctypes.c_void_p), ("lam", ctypes.c_double),
                 ("n0", ctypes.c_void_p), ("n_out", ctypes.c_void_p), ("t_end", ctypes.c_double),
                 ("rtol", ctypes.c_double), ("atol", ctypes.c_double),
-                ("log", ctypes.c_void_p), ("log_cap", ctypes.c_int64)]
+                ("log", ctypes.c_void_p), ("log_cap", ctypes.c_int64),
+                ("source", ctypes.c_void_p)]
 
 
 def lib():
@@ -67,6 +69,7 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         i64, i32, d, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
         L.smol_rhs.argtypes = [i64, i32, vp, vp, d, vp, vp, i32, vp]
+        L.smol_rhs_ex.argtypes = [i64, i32, vp, vp, d, vp, vp, vp, i32, vp]
         L.smol_integrate.argtypes = [i64, i32, vp, vp, d, vp, d, d, d, i32, i32, vp,
                                      ctypes.POINTER(_Stats), vp]
         L.smol_integrate_ex.argtypes = [i64, i32, vp, vp, d, vp, d, d, d, i32, i32,
@@ -139,8 +142,9 @@ def _raise(rc, what):
         raise SmolError(rc, what)
 
 
-def rhs(U, V, lam, n, out=None, precision="fp64"):
-    """dn/dt = S(n) of the truncated aggregation-shattering system."""
+def rhs(U, V, lam, n, out=None, precision="fp64", source=None):
+    """dn/dt = S(n) of the truncated aggregation-shattering system, plus the
+    constant sources of Eq. (3) when `source` (M doubles) is given."""
     _check(n, "n")
     M = n.numel()
     U, V, R = _factors(U, V, M)
@@ -148,17 +152,26 @@ def rhs(U, V, lam, n, out=None, precision="fp64"):
         out = torch.empty_like(n)
     _check(out, "out", numel=M)
     with torch.cuda.device(n.device):
-        rc = lib().smol_rhs(M, R, U.data_ptr(), V.data_ptr(), float(lam), n.data_ptr(),
-                            out.data_ptr(), PRECISIONS[precision], _stream(n))
+        if source is None:
+            rc = lib().smol_rhs(M, R, U.data_ptr(), V.data_ptr(), float(lam), n.data_ptr(),
+                                out.data_ptr(), PRECISIONS[precision], _stream(n))
+        else:
+            _check(source, "source", numel=M)
+            rc = lib().smol_rhs_ex(M, R, U.data_ptr(), V.data_ptr(), float(lam), n.data_ptr(),
+                                   source.data_ptr(), out.data_ptr(), PRECISIONS[precision],
+                                   _stream(n))
     _raise(rc, "smol_rhs")
     return out
 
 
 def _options(h0=0.0, h_min=0.0, max_steps=0, alpha=None, beta=None, controller="pi",
-             log=None, safety=0.0):
+             log=None, safety=0.0, source=None):
     o = _Options()
     o.h0, o.h_min, o.max_steps = float(h0), float(h_min), int(max_steps)
     o.safety = float(safety)
+    if source is not None:
+        _check(source, "source")
+        o.source = source.data_ptr()
     if alpha is not None or beta is not None:
         if alpha is None or beta is None:
             raise ValueError("give both alpha and beta, or neither")
@@ -225,6 +238,10 @@ def integrate_batch(instances, method="bs3", precision="fp64", **opts):
             if log.dim() != 2 or log.shape[1] != 9:
                 raise ValueError("log must be (rows, 9) float64")
             arr[i].log, arr[i].log_cap = log.data_ptr(), log.shape[0]
+        src = d.get("source")
+        if src is not None:
+            _check(src, "source", numel=M)
+            arr[i].source = src.data_ptr()
     o = _options(**opts)
     st = (_Stats * max(n, 1))()
     with torch.cuda.device(dev):

@@ -159,6 +159,7 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
         int rc = check_common(q.M, q.R, q.U, q.V, q.lambda);
         if (rc) return rc;
         if (!q.n0 || !q.n_out || (q.log && q.log_cap < 0)) return SMOL_EINVAL;
+        if (q.source && q.source == q.n_out) return SMOL_EINVAL;
         if (!(q.rtol > 0) || !(q.atol >= 0) || !(q.t_end >= 0) || !std::isfinite(q.t_end))
             return SMOL_EINVAL;
     }
@@ -200,7 +201,7 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
         const int64_t L = 1LL << logL, half = L / 2, N2 = 1LL << (logL / 2);
         const int64_t Mt = q.M > half + 1 ? q.M : half + 1;
         br.off[i] = at;
-        at += align256(sizeof(double) * (size_t)Mt * 10);                 // state, stages
+        at += align256(sizeof(double) * (size_t)Mt * 11);                 // state, stages, sources
         at += align256(sizeof(double) * (size_t)Mt * 2 * q.R);            // U, V copies
         at += align256(sizeof(cd) * (size_t)(q.R * L + L / 2));           // spectra
         at += align256(sizeof(double) * (size_t)(N2 * q.R * 4 + 4 * q.R + N2 * SMOL_EPART));
@@ -236,7 +237,7 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
             const int64_t Mt = q.M > half + 1 ? q.M : half + 1;
             char *p = arena + br.off[i];
             double *ibuf = (double *)p;
-            p += align256(sizeof(double) * (size_t)Mt * 10);
+            p += align256(sizeof(double) * (size_t)Mt * 11);
             double *uvt = (double *)p;
             p += align256(sizeof(double) * (size_t)Mt * 2 * q.R);
             cd *Z = (cd *)p;
@@ -255,6 +256,7 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
             I.nb[1] = ibuf + Mt;
             for (int j = 0; j < 7; ++j) I.kslot[j] = ibuf + (2 + j) * Mt;
             I.ybuf = ibuf + 9 * Mt;
+            I.src = ibuf + 10 * Mt;
             I.Z = Z;
             I.Qp = Z + q.R * L;
             I.red_part = red_part;
@@ -275,6 +277,7 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
             c.log = q.log;
             c.log_cap = q.log ? q.log_cap : 0;
             ctl_setup(c, method, o, q.rtol, q.atol);
+            c.has_src = q.source != nullptr;
             c.done = q.t_end == 0.0;  // nothing to do: n_out = n0
         }
         // ---- tables
@@ -325,6 +328,9 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
             hipLaunchKernelGGL(k_to_tr, dim3(128), dim3(256), 0, s, q.U, I.Ut, q.M, q.R, q.M, I.Mt, I.logL);
             hipLaunchKernelGGL(k_to_tr, dim3(128), dim3(256), 0, s, q.V, I.Vt, q.M, q.R, q.M, I.Mt, I.logL);
             hipLaunchKernelGGL(k_to_tr, dim3(128), dim3(256), 0, s, q.n0, I.nb[0], q.M, 1, q.M, I.Mt, I.logL);
+            if (q.source)
+                hipLaunchKernelGGL(k_to_tr, dim3(128), dim3(256), 0, s, q.source, I.src, q.M, 1, q.M,
+                                   I.Mt, I.logL);
         }
         // ---- starting step for every instance
         if (ids.empty()) {

@@ -96,6 +96,7 @@ struct IntegCtl {
     // the paper's controllers: Euclidean error norm (sc = tol), Eq. (6) safety
     int32_t l2;
     double paper_s;
+    int32_t has_src;  // Eq. (3) sources present
 };
 
 // Step factor of the paper's rules (Sec. 2): Fehlberg's fifth-root rule
@@ -118,6 +119,7 @@ struct IntegDev {
     double *nb[2];
     double *kslot[8];
     double *ybuf;
+    double *src;      // transposed sources (used when the control block says so)
     void *Z, *Qp;
     double *red_part, *red, *epart;
     Roots rt;
@@ -140,6 +142,7 @@ __device__ __forceinline__ RhsPlanDev plan_of(const IntegDev &I, const IntegCtl 
     P.Qp = I.Qp;
     P.red_part = I.red_part;
     P.red = I.red;
+    P.src = c.has_src ? I.src : nullptr;
     P.rt = I.rt;
     return P;
 }

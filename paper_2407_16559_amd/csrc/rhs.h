@@ -57,6 +57,7 @@ struct RhsPlanDev {
     void *Qp;             // L / 2 complex
     double *red_part;     // [jobs][R][4]
     double *red;          // [R][4]: w, t, r, p
+    const double *src;    // constant sources P_s of Eq. (3) (plan layout) or null
     Roots rt;
 };
 
@@ -403,13 +404,13 @@ struct PhaseC {
         const int rp = R < RPRE ? R : RPRE;
         // ---- prefetch every per-size input of this thread's outputs
         int64_t qv[PP], sz[PP];
-        double yv[PP], nv[PP], kv[PP][KMAX], Uv[PP][RPRE], Vv[PP][RPRE];
+        double yv[PP], nv[PP], sv[PP], kv[PP][KMAX], Uv[PP][RPRE], Vv[PP][RPRE];
 #pragma unroll
         for (int j = 0; j < PP; ++j) {
             const int e = tid + j * NT;
             qv[j] = -1;
             sz[j] = 0;
-            yv[j] = nv[j] = 0.0;
+            yv[j] = nv[j] = sv[j] = 0.0;
             if (e < NPOS) {
                 const int b = e % (N1 / 2), hh = (e / (N1 / 2)) & 1, f = e / N1;
                 const int64_t m = unit * COLS + f + hh * HALF + (int64_t)N2 * b;
@@ -418,6 +419,7 @@ struct PhaseC {
                     qv[j] = q;
                     sz[j] = m + 2;
                     yv[j] = ep.y[q];
+                    if (P.src) sv[j] = P.src[q];
                     if (need_n) nv[j] = ep.n[q];
 #pragma unroll
                     for (int k = 0; k < KMAX; ++k)
@@ -459,6 +461,7 @@ struct PhaseC {
                 pairs = fma(pp, q, fma(r, t, pairs));
             }
             S1 = -y1 * d1 + 0.5 * lam * pairs + lam * y1 * g1;
+            if (P.src) S1 += P.src[0];
         }
         // ---- inputs of this wave slot's first column-pass transform
         ColPre pre;
@@ -505,7 +508,7 @@ struct PhaseC {
                     if (a < rp) dsum = fma(Uv[j][a], wred[a], dsum);
                 for (int a = RPRE; a < R; ++a)
                     dsum = fma(P.U[(int64_t)a * P.ustride + qv[j]], P.red[4 * a], dsum);
-                const double S = fma(-(1.0 + lam) * yv[j], dsum, 0.5 * c);
+                const double S = fma(-(1.0 + lam) * yv[j], dsum, 0.5 * c) + sv[j];
                 yn[j] = finish(ep, qv[j], (double)sz[j], S, yv[j], nv[j], kv[j], nk, acc);
             }
         }

@@ -61,7 +61,7 @@ struct Plan {
     double *red_part = nullptr, *red = nullptr, *epart = nullptr;
     // integration state (allocated on first use)
     int64_t Mt = 0;                // vector length in the transposed layout
-    double *ibuf = nullptr;        // nb[2], kslot[7], ybuf: 10 Mt doubles
+    double *ibuf = nullptr;        // nb[2], kslot[7], ybuf, sources: 11 Mt doubles
     double *uvt = nullptr;         // transposed U and V: 2 R Mt doubles
     IntegCtl *ctl = nullptr;       // device control block
     IntegCtl *host = nullptr;      // pinned mirror
@@ -222,6 +222,7 @@ RhsPlanDev dev_plan(const Plan *p, const DevRoots *r, const double *U, const dou
     d.Qp = p->Qp;
     d.red_part = p->red_part;
     d.red = p->red;
+    d.src = nullptr;
     d.rt.tw = r->tw;
     d.rt.fine = r->fine;
     return d;
@@ -261,7 +262,7 @@ int alloc_integ(Plan *p)
     if (p->ibuf) return SMOL_OK;
     const int64_t half = 1LL << (p->logL - 1);
     p->Mt = p->M > half + 1 ? p->M : half + 1;
-    if (hipMalloc(&p->ibuf, sizeof(double) * (size_t)p->Mt * 10) != hipSuccess) return SMOL_ENOMEM;
+    if (hipMalloc(&p->ibuf, sizeof(double) * (size_t)p->Mt * 11) != hipSuccess) return SMOL_ENOMEM;
     if (hipMalloc(&p->uvt, sizeof(double) * (size_t)p->Mt * 2 * p->R) != hipSuccess) return SMOL_ENOMEM;
     if (hipMalloc(&p->ctl, sizeof(IntegCtl)) != hipSuccess) return SMOL_ENOMEM;
     HIP_TRY(hipHostMalloc(&p->host, sizeof(IntegCtl), hipHostMallocDefault));
@@ -284,6 +285,7 @@ IntegDev integ_dev(const Plan *p, const DevRoots *r)
     for (int j = 0; j < 7; ++j) I.kslot[j] = p->ibuf + (2 + j) * p->Mt;
     I.kslot[7] = nullptr;
     I.ybuf = p->ibuf + 9 * p->Mt;
+    I.src = p->ibuf + 10 * p->Mt;
     I.Z = p->Z;
     I.Qp = p->Qp;
     I.red_part = p->red_part;
@@ -350,12 +352,13 @@ SMOL_HIDDEN int check_common(int64_t M, int32_t R, const double *U, const double
 // C ABI
 // --------------------------------------------------------------------------
 
-extern "C" int smol_rhs(int64_t M, int32_t R, const double *U, const double *V, double lambda,
-                        const double *n, double *dndt, int32_t precision, void *stream)
+extern "C" int smol_rhs_ex(int64_t M, int32_t R, const double *U, const double *V, double lambda,
+                           const double *n, const double *source, double *dndt, int32_t precision,
+                           void *stream)
 {
     int rc = check_common(M, R, U, V, lambda);
     if (rc) return rc;
-    if (!n || !dndt || n == dndt) return SMOL_EINVAL;
+    if (!n || !dndt || n == dndt || source == dndt) return SMOL_EINVAL;
     if (precision != SMOL_FP64 && precision != SMOL_FP32X2) return SMOL_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     Plan *p;
@@ -363,12 +366,19 @@ extern "C" int smol_rhs(int64_t M, int32_t R, const double *U, const double *V, 
     if ((rc = get_plan(M, R, precision, &p))) return rc;
     if ((rc = get_roots(p->dev, &r))) return rc;
     RhsPlanDev P = dev_plan(p, r, U, V, lambda);
+    P.src = source;
     Pro in{A_COMBINE, n, nullptr, 0.0, nullptr};
     Epi ep{};
     ep.mode = C_RHS;
     ep.y = n;
     ep.out = dndt;
     return launch_rhs(p, P, in, ep, (hipStream_t)stream);
+}
+
+extern "C" int smol_rhs(int64_t M, int32_t R, const double *U, const double *V, double lambda,
+                        const double *n, double *dndt, int32_t precision, void *stream)
+{
+    return smol_rhs_ex(M, R, U, V, lambda, n, nullptr, dndt, precision, stream);
 }
 
 extern "C" int smol_release_plans(void)
@@ -448,6 +458,7 @@ extern "C" int smol_integrate_ex(int64_t M, int32_t R, const double *U, const do
     c.log = o.log;
     c.log_cap = o.log ? o.log_cap : 0;
     ctl_setup(c, method, o, rtol, atol);
+    c.has_src = o.source != nullptr;
     if (o.controller == SMOL_CTRL_LEARNED) {
         c.mlp = proposer_weights(p->dev);
         if (!c.mlp) return SMOL_EINVAL;  // smol_proposer_set first
@@ -457,6 +468,9 @@ extern "C" int smol_integrate_ex(int64_t M, int32_t R, const double *U, const do
     hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, U, I.Ut, M, R, M, I.Mt, p->logL);
     hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, V, I.Vt, M, R, M, I.Mt, p->logL);
     hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, n0, I.nb[0], M, 1, M, I.Mt, p->logL);
+    if (o.source)
+        hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, o.source, I.src, M, 1, M, I.Mt,
+                           p->logL);
     const int nC = p->dC.jobs;
     // starting step: S(n0), h0, S(n0 + h0 f0), h
     if ((rc = launch_stage(p, I, method, 0, 0, s))) return rc;

@@ -1,0 +1,117 @@
+"""Constant sources of Eq. (3) on the GPU: the right-hand side S(n) + P
+against the oracle, adaptive runs (embedded pairs and the paper's schemes)
+taking the oracle's decisions, batched runs equal to single runs, and the
+paper's two-source workload (P_1 = 1, P_100 = p) measured."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_util import normwise, say, t
+from test_oracle_sources import two_sources
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def smol():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2407_16559_amd as smol
+    return smol
+
+
+@pytest.mark.parametrize("M,precision", [(150, "fp64"), (5000, "fp64"), (5000, "fp32x2")])
+def test_rhs_with_sources(smol, M, precision):
+    U, V = W.random_factors(M, 3, seed=M)
+    n = W.random_state(M, seed=M + 1)
+    P = two_sources(M, 0.4)
+    got = smol.rhs(t(U), t(V), 0.02, t(n), precision=precision, source=t(P)).cpu().numpy()
+    ref = oracle.rhs_source(U, V, 0.02, n, P)
+    err = normwise(got, ref)
+    say(f"rhs with sources M={M} {precision}: normwise error {err:.2e}")
+    assert err < 1e-10
+
+
+@pytest.mark.parametrize("method,name", [("bs3", oracle.BS32), ("dp5", oracle.DP54)])
+def test_embedded_run_with_sources(smol, method, name):
+    import torch
+    M = 250
+    U, V = W.constant_kernel(M)
+    n0 = W.monodisperse(M)
+    P = two_sources(M, 0.2)
+    log = torch.zeros((5000, 9), dtype=torch.float64, device="cuda:0")
+    out, st = smol.integrate(t(U), t(V), 0.0, t(n0), 20.0, 1e-6, 1e-10, method=method, h0=1.0,
+                             log=log, source=t(P))
+    ref, rst, rlog = oracle.integrate(U, V, 0.0, n0, 20.0, 1e-6, 1e-10, method=name, h0=1.0,
+                                      log_cap=5000, source=P)
+    g = log.cpu().numpy()[: len(rlog)]
+    assert (st["n_accept"], st["n_reject"]) == (rst["n_accept"], rst["n_reject"])
+    np.testing.assert_array_equal(g[:, 3], rlog[:, 3])
+    # step factors follow err, a small difference of solutions: over hundreds
+    # of attempts t and h drift apart at the 1e-9 level
+    np.testing.assert_allclose(g[:, [0, 1]], rlog[:, [0, 1]], rtol=1e-7)
+    assert normwise(out.cpu().numpy(), ref) < 1e-9
+
+
+def test_paper_scheme_with_sources(smol):
+    import torch
+    M = 250
+    U, V = W.brownian_rank3(M, 1.0 / 3.0)
+    n0 = W.monodisperse(M)
+    P = two_sources(M, 0.1)
+    log = torch.zeros((5000, 9), dtype=torch.float64, device="cuda:0")
+    out, st = smol.integrate(t(U), t(V), 0.0, t(n0), 20.0, 1e-7, 0.0, method="rkf45",
+                             controller="fehlberg", log=log, source=t(P))
+    ref, rst, rlog = oracle.integrate_paper(U, V, 0.0, n0, 20.0, 1e-7, oracle.RKF45,
+                                            oracle.RULE_FEHLBERG, log_cap=5000, source=P)
+    g = log.cpu().numpy()[: len(rlog)]
+    assert (st["n_accept"], st["n_reject"]) == (rst["n_accept"], rst["n_reject"])
+    np.testing.assert_array_equal(g[:, 3], rlog[:, 3])
+    np.testing.assert_allclose(g[:, [0, 1]], rlog[:, [0, 1]], rtol=1e-6)
+    assert normwise(out.cpu().numpy(), ref) < 1e-9
+
+
+def test_batch_with_sources(smol):
+    insts = []
+    for M, p in ((300, 0.0), (2000, 0.3), (4500, 0.1)):
+        U, V = W.brownian_rank3(M, 0.3)
+        insts.append(dict(U=t(U), V=t(V), lam=0.0, n0=t(W.monodisperse(M)), t_end=15.0,
+                          rtol=1e-6, atol=1e-12, source=t(two_sources(M, p))))
+    insts.append(dict(insts[0], source=None))  # one without sources
+    outs, stats = smol.integrate_batch(insts, method="dp5")
+    for d, o, st in zip(insts, outs, stats):
+        r, rs = smol.integrate(d["U"], d["V"], 0.0, d["n0"], 15.0, 1e-6, 1e-12, method="dp5",
+                               source=d["source"])
+        assert st == rs and np.array_equal(o.cpu().numpy(), r.cpu().numpy())
+    assert not np.array_equal(outs[0].cpu().numpy(), outs[-1].cpu().numpy())
+
+
+def test_two_source_workload(smol):
+    """The paper's sources workload (Sec. 3.1, Tables 1-2): M = 32768,
+    P_1 = 1, P_100 = p, monodisperse start, t = 0 -> 1000, K == 1 (rank 1)
+    and the Brownian kernel with alpha = 1/3 (rank 2, no constant term).
+    The paper does not give p; p = 0.05 here.  RHS evaluations and wall
+    time are reported for RK2 with step doubling, RKF45 and DP5(4)."""
+    M, p = 32768, 0.05
+    P = t(two_sources(M, p))
+    n0 = t(W.monodisperse(M))
+    kernels = {"K=1": W.constant_kernel(M), "Brownian 1/3": W.brownian_rank2(M, 1.0 / 3.0)}
+    for kname, (U, V) in kernels.items():
+        for method, ctrl in (("rk2_dbl", "step_doubling"), ("rkf45", "fehlberg"), ("dp5", "pi")):
+            row = []
+            for tol in (1e-4, 1e-6, 1e-8):
+                import torch
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                atol = 0.0 if ctrl != "pi" else tol * 1e-6
+                _, st = smol.integrate(t(U), t(V), 0.0, n0, 1000.0, tol, atol, method=method,
+                                       controller=ctrl, source=P, max_steps=2000000)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                assert st["status"] == 0
+                row.append(f"{dt:.2f} s / {st['n_rhs']}")
+            say(f"{kname} {method}/{ctrl}: tol 1e-4, 1e-6, 1e-8 -> " + "; ".join(row))
