@@ -287,6 +287,15 @@ __device__ inline void block_sum_epart(const double *ep, int njobs, double *tot)
 #define MLP_LOG_FMIN (-1.6094379124341003)  // log 0.2
 #define MLP_LOG_FMAX (2.302585092994046)    // log 10
 
+// log of the PI factor clamp(0.9 err^-alpha err_prev^beta, 0.2, 10)
+// (err = 0: 10), the base the learned proposer corrects.
+__host__ __device__ inline double pi_log_factor(double err, double err_prev, double alpha,
+                                                double beta)
+{
+    const double fac = err == 0.0 ? 10.0 : 0.9 * pow(err, -alpha) * pow(err_prev, beta);
+    return log(fmin(fmax(fac, 0.2), 10.0));
+}
+
 // Features: log-moments of the new state / 40, log h / 10, log of the last
 // four error norms (most recent first, missing ones 0) / 10.
 __device__ __forceinline__ void proposer_features(const double *mom, double h, const double *hist,
@@ -410,7 +419,8 @@ __device__ inline void controller_step(const IntegDev &I, int njobs)
             const float y = mlp_forward_block(c.mlp, x);
             if (isfinite(y)) {
                 learned = true;
-                dlog = fmin(fmax((double)y, MLP_LOG_FMIN), MLP_LOG_FMAX);
+                const double base = pi_log_factor(err, c.err_prev, c.alpha, c.beta);
+                dlog = fmin(fmax(base + (double)y, MLP_LOG_FMIN), MLP_LOG_FMAX);
             }
         }
     }

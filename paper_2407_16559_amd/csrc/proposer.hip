@@ -19,7 +19,8 @@ SMOL_HIDDEN const float *proposer_weights(int dev)
 // ---- dataset: features of the decision after each accepted attempt and
 // the hindsight target: the step that would have given err = err_target on
 // the next attempt, log(h_{j+1}/h_j) + (1/k) log(err_target / err_{j+1}),
-// clamped.
+// clamped, less the PI controller's log factor at that decision (default
+// exponents): the network learns a correction to PI.
 // Log rows: (t, h, err, accepted, t_after, M0, M1, M2, M3).
 __global__ void k_dataset_flags(const double *rec, int64_t rows, int *flag, int *count)
 {
@@ -28,7 +29,11 @@ __global__ void k_dataset_flags(const double *rec, int64_t rows, int *flag, int 
     int ok = 0;
     if (j + 1 < rows) {
         const double *r = rec + j * 9, *n = r + 9;
-        ok = r[3] == 1.0 && n[2] > 0.0 && isfinite(n[2]) && r[1] > 0.0 && n[1] > 0.0;
+        // the network decides only after an accepted attempt that did not
+        // follow a rejection
+        const bool after_reject = j > 0 && rec[(j - 1) * 9 + 3] != 1.0;
+        ok = r[3] == 1.0 && !after_reject && n[2] > 0.0 && isfinite(n[2]) && r[1] > 0.0 &&
+             n[1] > 0.0;
     }
     if (j < rows) flag[j] = ok;
     sc[threadIdx.x] = ok;
@@ -59,7 +64,15 @@ __global__ void k_dataset_rows(const double *rec, int64_t rows, int k, double er
     for (int q = 0; q < MLP_NIN; ++q) X[o * MLP_NIN + q] = x[q];
     double d = log(n[1] / r[1]) + log(err_target / n[2]) / (double)k;
     d = fmin(fmax(d, MLP_LOG_FMIN), MLP_LOG_FMAX);
-    target[o] = (float)d;
+    // the network corrects the PI step the run took: err_prev is the last
+    // accepted attempt's err before j (floored at 1e-4; 1 before the first)
+    double err_prev = 1.0;
+    for (int64_t i = j - 1; i >= 0; --i)
+        if (rec[i * 9 + 3] == 1.0) {
+            err_prev = fmax(rec[i * 9 + 2], 1e-4);
+            break;
+        }
+    target[o] = (float)(d - pi_log_factor(r[2], err_prev, 0.7 / k, 0.4 / k));
 }
 
 // ---- training -----------------------------------------------------------

@@ -88,7 +88,8 @@ def test_training_reduces_loss(smol):
 
 def test_dataset_rows_match_oracle_features(smol):
     """Features of the decision after attempt j equal the oracle's features of
-    the state reached after attempt j (run again with max_steps = j+1)."""
+    the state reached after attempt j (run again with max_steps = j+1); the
+    target is the hindsight log step ratio less PI's log factor."""
     import torch
     M = 800
     U, V = W.brownian_rank3(M, 0.4)
@@ -98,7 +99,8 @@ def test_dataset_rows_match_oracle_features(smol):
     rows = st["n_accept"] + st["n_reject"]
     X, tg = smol.proposer_dataset(log, rows, "dp5")
     L = log.cpu().numpy()[:rows]
-    acc = [j for j in range(rows - 1) if L[j, 3] == 1]
+    # rows: accepted attempts with a successor that did not follow a rejection
+    acc = [j for j in range(rows - 1) if L[j, 3] == 1 and (j == 0 or L[j - 1, 3] == 1)]
     assert X.shape[0] == len(acc)
     for r, j in list(enumerate(acc))[5::7][:6]:
         nj, sj = smol.integrate(t(U), t(V), 0.02, t(n0), 20.0, 1e-6, 1e-12, method="dp5",
@@ -106,8 +108,13 @@ def test_dataset_rows_match_oracle_features(smol):
         hist = [L[j - q, 2] for q in range(4) if j - q >= 0]
         ref = oracle.features(nj.cpu().numpy(), L[j, 1], hist)
         np.testing.assert_allclose(X[r].cpu().numpy(), ref, rtol=2e-6, atol=2e-7)
-        want = np.log(L[j + 1, 1] / L[j, 1]) + np.log(0.8 / L[j + 1, 2]) / 5
-        assert abs(tg[r].item() - np.clip(want, np.log(0.2), np.log(10))) < 1e-5
+        # hindsight log step ratio, less the PI log factor the run applied
+        want = np.clip(np.log(L[j + 1, 1] / L[j, 1]) + np.log(0.8 / L[j + 1, 2]) / 5,
+                       np.log(0.2), np.log(10))
+        prev = [L[i, 2] for i in range(j) if L[i, 3] == 1]
+        err_prev = max(prev[-1], 1e-4) if prev else 1.0
+        pi = np.log(np.clip(0.9 * L[j, 2] ** -0.14 * err_prev ** 0.08, 0.2, 10.0))
+        assert abs(tg[r].item() - (want - pi)) < 1e-5
 
 
 def test_bad_proposer_falls_back_to_pi(smol):
