@@ -208,10 +208,11 @@ int smol_integrate_batch(int32_t n_inst, const smol_instance *inst,
  * W2[64][64], b2[64], W3[64], b3).  Features at the decision after an
  * accepted attempt: log M0..log M3 of the new state divided by 40, log h
  * divided by 10, log err of the last four attempts (most recent first,
- * missing ones 0) divided by 10.  Output: log(h_next / h), clamped to
- * [log 0.2, log 10]; right after a rejection, or for non-finite features,
- * the PI rule is used instead (counted in smol_stats.n_fallback).  The
- * embedded error estimate still accepts or rejects every step. */
+ * missing ones 0) divided by 10.  Output y: a correction to the PI rule,
+ * log(h_next / h) = log(PI factor) + y, clamped to [log 0.2, log 10]; right
+ * after a rejection, or for non-finite features or output, the PI rule alone
+ * is used (counted in smol_stats.n_fallback).  The embedded error estimate
+ * still accepts or rejects every step. */
 
 /* Install the weights used by learned-mode runs on the current device
  * (device pointer, copied; n_params must be 4865).  Synchronous. */
@@ -239,11 +240,12 @@ int smol_proposer_train(const float *X, const float *target, int64_t n_rows,
 
 /* Training rows from a run's per-attempt log (device, rows x 9 doubles as
  * written by smol_integrate_ex): one row per accepted attempt j that has a
- * successor, features as above and target
- *   log(h_{j+1}/h_j) + (1/k) log(err_target / err_{j+1})
- * (k = embedded order + 1), the ratio that would have hit err = err_target
- * (0 < err_target <= 1; 0.8 is the default reading) on the next attempt,
- * clamped.
+ * successor and does not follow a rejection, features as above and target
+ *   clamp(log(h_{j+1}/h_j) + (1/k) log(err_target / err_{j+1})) - log(PI_j)
+ * (k = embedded order + 1): the log ratio that would have hit
+ * err = err_target (0 < err_target <= 1; 0.8 is the default reading) on the
+ * next attempt, clamped to [log 0.2, log 10], less the log factor the PI rule
+ * with the default exponents (0.7/k, 0.4/k) gives at that decision.
  * X (rows x 9) and target (rows) are device buffers of capacity `rows`;
  * *n_out (host) receives the number of rows written.  Synchronous. */
 int smol_proposer_dataset(const double *log, int64_t rows, int32_t method,
