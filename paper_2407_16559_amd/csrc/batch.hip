@@ -198,7 +198,7 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
         }
         nC[i] = d[PH_C].jobs;
         redA[i] = d[PH_A].jobs;
-        const int64_t L = 1LL << logL, half = L / 2, N2 = 1LL << (logL / 2);
+        const int64_t L = 1LL << logL, half = L / 2, N2 = 1LL << split_log_n2(logL);
         const int64_t Mt = q.M > half + 1 ? q.M : half + 1;
         br.off[i] = at;
         at += align256(sizeof(double) * (size_t)Mt * 11);                 // state, stages, sources
@@ -233,7 +233,7 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
         for (int i = 0; i < n_inst; ++i) {
             const smol_instance &q = inst[i];
             const int logL = br.logL[i];
-            const int64_t L = 1LL << logL, half = L / 2, N2 = 1LL << (logL / 2);
+            const int64_t L = 1LL << logL, half = L / 2, N2 = 1LL << split_log_n2(logL);
             const int64_t Mt = q.M > half + 1 ? q.M : half + 1;
             char *p = arena + br.off[i];
             double *ibuf = (double *)p;

@@ -10,6 +10,11 @@
 #define SMOL_TW (1 << SMOL_LOG_TW)
 #define SMOL_LOG_LMAX 20       // longest convolution transform: 2^20
 
+// Four-step split of a transform of length L = 2^logL into N1 x N2: log2 of
+// the column length N1 (the rest, N2 = L / N1, is the row length).
+__host__ __device__ constexpr int split_log_n1(int logL) { return (logL + 1) / 2; }
+__host__ __device__ constexpr int split_log_n2(int logL) { return logL - split_log_n1(logL); }
+
 struct __align__(16) cd {
     double x, y;
 };

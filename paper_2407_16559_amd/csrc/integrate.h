@@ -131,8 +131,8 @@ __device__ __forceinline__ RhsPlanDev plan_of(const IntegDev &I, const IntegCtl 
     P.M = I.M;
     P.R = I.R;
     P.logL = I.logL;
-    P.logN1 = (I.logL + 1) / 2;
-    P.logN2 = I.logL / 2;
+    P.logN1 = split_log_n1(I.logL);
+    P.logN2 = split_log_n2(I.logL);
     P.tr = 1;
     P.ustride = I.Mt;
     P.lam = c.lam;
@@ -143,6 +143,26 @@ __device__ __forceinline__ RhsPlanDev plan_of(const IntegDev &I, const IntegCtl 
     P.red_part = I.red_part;
     P.red = I.red;
     P.src = c.has_src ? I.src : nullptr;
+    P.rt = I.rt;
+    return P;
+}
+
+// The plan fields the row-pair pass uses (transform shape, workspaces,
+// roots), which do not depend on the control block.
+__device__ __forceinline__ RhsPlanDev plan_of_ws(const IntegDev &I)
+{
+    RhsPlanDev P{};
+    P.M = I.M;
+    P.R = I.R;
+    P.logL = I.logL;
+    P.logN1 = split_log_n1(I.logL);
+    P.logN2 = split_log_n2(I.logL);
+    P.tr = 1;
+    P.ustride = I.Mt;
+    P.Z = I.Z;
+    P.Qp = I.Qp;
+    P.red_part = I.red_part;
+    P.red = I.red;
     P.rt = I.rt;
     return P;
 }

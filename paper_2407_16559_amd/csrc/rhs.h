@@ -64,7 +64,7 @@ struct RhsPlanDev {
 // position of size index idx (0-based) in the transposed layout
 __host__ __device__ __forceinline__ int64_t pos_tr(int64_t idx, int logL)
 {
-    const int logN1 = (logL + 1) / 2, logN2 = logL / 2;
+    const int logN1 = split_log_n1(logL), logN2 = split_log_n2(logL);
     const int64_t half = 1LL << (logL - 1);
     if (idx >= half) return half;
     return ((idx & ((1LL << logN2) - 1)) << (logN1 - 1)) + (idx >> logN2);
@@ -531,6 +531,12 @@ struct PhaseC {
             }
             if (mono) ycol[(2 * COLS - 1) * (N1 / 2)] = yn1;
         }
+        if constexpr (FUSE) {
+            // the next column pass first: its spectra are the bulk of the
+            // kernel's stores, so they drain while the reductions run
+            __syncthreads();
+            column_pass(P, unit, lds, ycol, pre);
+        }
         if (mode == C_STAGE) {
             // reductions of the next stage state, four ranks per pass
             for (int a0 = 0; a0 < R; a0 += 4) {
@@ -586,10 +592,6 @@ struct PhaseC {
             __syncthreads();
             if (tid < SMOL_EPART)
                 ep.epart[(int64_t)unit * SMOL_EPART + tid] = sum_waves<W>(sh, SMOL_EPART, tid);
-        }
-        if constexpr (FUSE) {
-            __syncthreads();
-            column_pass(P, unit, lds, ycol, pre);
         }
     }
 

@@ -58,26 +58,28 @@ template <class F, int PH, class... Args>
 int with_variant(int logL, int precision, int v, Args &&...args)
 {
     switch (logL) {
-#define CASE(LL, A, B)                                                                  \
+#define CASE(LL)                                                                        \
     case LL:                                                                            \
         return precision == SMOL_FP32X2                                                 \
-                   ? run_variant<F, PH, LL, (1 << A), (1 << B), cff>(v, args...)        \
-                   : run_variant<F, PH, LL, (1 << A), (1 << B), cd>(v, args...);
-        CASE(6, 3, 3)
-        CASE(7, 4, 3)
-        CASE(8, 4, 4)
-        CASE(9, 5, 4)
-        CASE(10, 5, 5)
-        CASE(11, 6, 5)
-        CASE(12, 6, 6)
-        CASE(13, 7, 6)
-        CASE(14, 7, 7)
-        CASE(15, 8, 7)
-        CASE(16, 8, 8)
-        CASE(17, 9, 8)
-        CASE(18, 9, 9)
-        CASE(19, 10, 9)
-        CASE(20, 10, 10)
+                   ? run_variant<F, PH, LL, (1 << split_log_n1(LL)),                    \
+                                 (1 << split_log_n2(LL)), cff>(v, args...)              \
+                   : run_variant<F, PH, LL, (1 << split_log_n1(LL)),                    \
+                                 (1 << split_log_n2(LL)), cd>(v, args...);
+        CASE(6)
+        CASE(7)
+        CASE(8)
+        CASE(9)
+        CASE(10)
+        CASE(11)
+        CASE(12)
+        CASE(13)
+        CASE(14)
+        CASE(15)
+        CASE(16)
+        CASE(17)
+        CASE(18)
+        CASE(19)
+        CASE(20)
 #undef CASE
     default: return SMOL_EUNSUPPORTED;
     }

@@ -174,8 +174,8 @@ int get_plan(int64_t M, int R, int precision, Plan **out)
     int logL = ilog2_ceil(2 * M - 2);
     if (logL < 6) logL = 6;
     p->logL = logL;
-    p->logN1 = (logL + 1) / 2;
-    p->logN2 = logL / 2;
+    p->logN1 = split_log_n1(logL);
+    p->logN2 = split_log_n2(logL);
     const int64_t L = 1LL << logL;
     const int64_t N2 = 1LL << p->logN2;
     hipError_t e = hipMalloc(&p->Z, sizeof(cd) * (size_t)(R * L + L / 2));
