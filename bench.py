@@ -24,7 +24,7 @@ HBM_PEAK = 8.0e12
 
 # sources of the right-hand-side kernels; hardware byte counts recorded in
 # profiles/ are used only while these files are unchanged
-KERNEL_SOURCES = ["common.h", "ff.h", "fft.h", "rhs.h", "kernels.h", "sched.h",
+KERNEL_SOURCES = ["common.h", "ff.h", "fft.h", "rhs.h", "integrate.h", "kernels.h", "sched.h",
                   "schedule_table.h", "phases_a.hip", "phases_b.hip", "phases_c.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_rhs_M65536_R3.md")
 
@@ -64,6 +64,28 @@ def rhs_bytes(M, R, L):
     b = 16 * L * R + 8 * L
     c = 8 * L + 8 * M + 8 * M * R + 8 * M
     return {"phase_a": a, "phase_b": b, "phase_c": c, "rhs": a + b + c}
+
+
+def step_bytes(M, R, L):
+    """Algorithmic HBM bytes of the integrator's stage kernels in a DP5(4)
+    attempt (FP64):
+      int_a        column pass of stage 2: reads n, k_1, U, V; writes y_2 and
+                   R packed spectra;
+      int_b        row-pair pass: reads the spectra, writes the packed inverse
+                   input;
+      int_c_fused  finish of stage 3 fused with the next column pass: reads the
+                   packed input, y_3, n, k_1, k_2, U, V; writes k_3, y_4 and the
+                   next spectra;
+      int_c_last   finish of stage 7: reads the packed input, n_new, n, the five
+                   stage vectors with nonzero error weights, U; writes k_7."""
+    return {"int_a": 24 * M + 16 * M * R + 16 * L * R,
+            "int_b": 16 * L * R + 8 * L,
+            "int_c_fused": 8 * L + 48 * M + 16 * M * R + 16 * L * R,
+            "int_c_last": 8 * L + 64 * M + 8 * M * R}
+
+
+# launches of each stage kernel per DP5(4) attempt (stages 2..7)
+STEP_LAUNCHES = {"int_a": 1, "int_b": 6, "int_c_fused": 5, "int_c_last": 1}
 
 
 def cpu_baseline(U, V, lam, n0, per_step_rhs):
@@ -166,21 +188,27 @@ def main():
     n_acc = sum(s["n_accept"] for s in stats)
     n_rhs = sum(s["n_rhs"] for s in stats)
 
-    # live per-kernel timing of one right-hand side (HIP events on the stream
-    # the kernels run on), at the run's final state
+    # live per-kernel timing (HIP events on the stream the kernels run on) of
+    # the integrator's stage kernels at the run's final state; the dominant
+    # kernel is the one with the largest share of an attempt
     logL = int(np.ceil(np.log2(2 * M - 2)))
     L = 1 << logL
-    prof = smol.profile_rhs(Ud, Vd, lam, out.clone(), iters=200)
-    nbytes = rhs_bytes(M, R, L)
-    dom = max(("phase_a", "phase_b", "phase_c"), key=lambda k: prof[k])
+    prof = smol.profile_step(Ud, Vd, lam, out.clone(), method="dp5", iters=200)
+    nbytes = step_bytes(M, R, L)
+    dom = max(STEP_LAUNCHES, key=lambda k: prof[k] * STEP_LAUNCHES[k])
     achieved = nbytes[dom] / (prof[dom] * 1e-3)
+    attempt_ms = sum(prof[k] * STEP_LAUNCHES[k] for k in STEP_LAUNCHES)
+    rhs = smol.profile_rhs(Ud, Vd, lam, out.clone(), iters=200)
+    rb = rhs_bytes(M, R, L)
     roof = {"bound": "hbm", "kernel": dom, "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
             "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": recorded_traffic(dom),
             "alg_bytes": nbytes[dom],
-            "ms_per_launch": {k: prof[k] for k in ("phase_a", "phase_b", "phase_c")},
-            "rhs_ms": prof["rhs"],
-            "rhs_alg_bytes": nbytes["rhs"],
-            "rhs_frac": nbytes["rhs"] / (prof["rhs"] * 1e-3) / HBM_PEAK}
+            "ms_per_launch": prof,
+            "launches_per_attempt": STEP_LAUNCHES,
+            "stage_kernels_ms_per_attempt": attempt_ms,
+            "share_of_stage_kernels": prof[dom] * STEP_LAUNCHES[dom] / attempt_ms,
+            "standalone_rhs": {"ms_per_launch": rhs, "alg_bytes": rb,
+                               "frac": rb["rhs"] / (rhs["rhs"] * 1e-3) / HBM_PEAK}}
 
     line = {
         "metric": "accepted RK steps/s (time-to-t_end at rtol 1e-6), M=2^16 R=3",
@@ -267,7 +295,8 @@ def bench_batch(args, smol, W, torch, dev):
 def bench_kernels(args, smol, W, torch, dev):
     """The three right-hand-side kernels of the large instance (M = 65536,
     at its start state), --steps launches of each and --steps whole RHS,
-    then --steps copies of a 64 MiB device buffer: the reference a hardware
+    --steps launches of each of the integrator's DP5(4) stage kernels at the
+    same state, then --steps copies of a 64 MiB device buffer: the reference a hardware
     byte counter is scaled by (each copy reads and writes 64 MiB)."""
     import numpy as np
     U, V, lam, n0 = W.config_instance(2)
@@ -275,6 +304,7 @@ def bench_kernels(args, smol, W, torch, dev):
     L = 1 << int(np.ceil(np.log2(2 * M - 2)))
     Ud, Vd, nd = (torch.from_numpy(x).to(dev) for x in (U, V, W.exponential_start(M, 300.0)))
     prof = smol.profile_rhs(Ud, Vd, lam, nd, iters=args.steps)
+    prof_step = smol.profile_step(Ud, Vd, lam, nd, method="dp5", iters=args.steps)
     nbytes = 64 << 20
     src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
     dst = torch.empty_like(src)
@@ -283,8 +313,9 @@ def bench_kernels(args, smol, W, torch, dev):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"workload": "kernels", "M": M, "R": R, "fft_length": L,
-                      "launches": args.steps, "ms_per_launch": prof,
-                      "alg_bytes": rhs_bytes(M, R, L), "copy_bytes_each_way": nbytes}),
+                      "launches": args.steps, "ms_per_launch": dict(prof, **prof_step),
+                      "alg_bytes": dict(rhs_bytes(M, R, L), **step_bytes(M, R, L)),
+                      "copy_bytes_each_way": nbytes}),
           flush=True)
 
 

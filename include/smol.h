@@ -263,6 +263,25 @@ int smol_profile_rhs(int64_t M, int32_t R, const double *U, const double *V,
                      double lambda, const double *n, double *dndt,
                      int32_t iters, float *ms_out, void *stream);
 
+/* Timing hook for the integrator's own stage kernels (the kernels a step
+ * attempt replays; Sec. 2, Eq. (5), with the right-hand side of Eq. (4)).
+ * Runs the starting step and one attempt's stages of `method` (SMOL_BS32 or
+ * SMOL_DP54, FP64, rtol 1e-6, atol 1e-12) from the state n0 (device, M
+ * doubles, natural layout) without a controller launch, then launches each
+ * kernel `iters` times back to back between HIP events on `stream`:
+ *   ms_out[0] column pass of stage 2 (forms y_2 = n + h a_21 k_1);
+ *   ms_out[1] row-pair spectral pass;
+ *   ms_out[2] inverse column pass + finish of stage 3 fused with the stage
+ *             4 state, its reductions and the next column pass;
+ *   ms_out[3] inverse column pass + finish of the last stage with the
+ *             error-norm and moment partials.
+ * ms_out is HOST memory (4 floats, mean milliseconds per launch).  The
+ * caller's arrays are only read.  EINVAL for bad sizes, pointers, lambda,
+ * iters < 1 or another method.  Synchronous. */
+int smol_profile_step(int64_t M, int32_t R, const double *U, const double *V,
+                      double lambda, const double *n0, int32_t method, int32_t iters,
+                      float *ms_out, void *stream);
+
 /* Launch schedules.  Each of the three right-hand-side kernels (column
  * pass A, row-pair pass B, inverse column pass + finish C) comes in up to
  * four variants that differ in the radix of the in-register butterflies and

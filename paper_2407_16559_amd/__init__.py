@@ -84,6 +84,8 @@ def lib():
                                           ctypes.c_float, ctypes.c_uint64, vp, vp]
         L.smol_profile_rhs.argtypes = [i64, i32, vp, vp, d, vp, vp, i32,
                                        ctypes.POINTER(ctypes.c_float), vp]
+        L.smol_profile_step.argtypes = [i64, i32, vp, vp, d, vp, i32, i32,
+                                        ctypes.POINTER(ctypes.c_float), vp]
         L.smol_set_schedule.argtypes = [i32, ctypes.POINTER(i32)]
         L.smol_get_schedule.argtypes = [i32, ctypes.POINTER(i32)]
         L.smol_autotune.argtypes = [i64, i32, vp, vp, d, vp, i32, i32, i32, ctypes.POINTER(i32),
@@ -328,6 +330,22 @@ def profile_rhs(U, V, lam, n, iters=50, out=None):
                                     out.data_ptr(), int(iters), ms, _stream(n))
     _raise(rc, "smol_profile_rhs")
     return {"phase_a": ms[0], "phase_b": ms[1], "phase_c": ms[2], "rhs": ms[3]}
+
+
+def profile_step(U, V, lam, n0, method="dp5", iters=50):
+    """Mean milliseconds per launch of the integrator's stage kernels at the
+    state n0: column pass of stage 2, row-pair pass, fused finish of stage 3
+    (with the next column pass) and the last stage's finish, timed with HIP
+    events on the current stream."""
+    _check(n0, "n0")
+    M = n0.numel()
+    U, V, R = _factors(U, V, M)
+    ms = (ctypes.c_float * 4)()
+    with torch.cuda.device(n0.device):
+        rc = lib().smol_profile_step(M, R, U.data_ptr(), V.data_ptr(), float(lam), n0.data_ptr(),
+                                     METHODS[method], int(iters), ms, _stream(n0))
+    _raise(rc, "smol_profile_step")
+    return {"int_a": ms[0], "int_b": ms[1], "int_c_fused": ms[2], "int_c_last": ms[3]}
 
 
 def set_schedule(logL, variants):

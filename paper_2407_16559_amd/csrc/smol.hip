@@ -579,6 +579,79 @@ extern "C" int smol_profile_rhs(int64_t M, int32_t R, const double *U, const dou
     return SMOL_OK;
 }
 
+// Times the integrator's own stage kernels at the state n0: the starting
+// step and one full attempt's stages run first (so every stage vector,
+// spectrum and reduction row holds real data), then each kernel is launched
+// iters times back to back between HIP events.  Relaunching a stage kernel
+// recomputes the same workspaces from the same inputs, except that the fused
+// finish of stage 3 reads and rewrites the stage state, which stays finite
+// for a stable step; the run's control block is never advanced (no
+// controller launch), so every launch does its full work.
+extern "C" int smol_profile_step(int64_t M, int32_t R, const double *U, const double *V,
+                                 double lambda, const double *n0, int32_t method, int32_t iters,
+                                 float *ms_out, void *stream)
+{
+    int rc = check_common(M, R, U, V, lambda);
+    if (rc) return rc;
+    if (!n0 || iters < 1 || !ms_out) return SMOL_EINVAL;
+    if (method != SMOL_BS32 && method != SMOL_DP54) return SMOL_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Plan *p;
+    DevRoots *r;
+    if ((rc = get_plan(M, R, SMOL_FP64, &p))) return rc;
+    if ((rc = get_roots(p->dev, &r))) return rc;
+    if ((rc = alloc_integ(p))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const IntegDev I = integ_dev(p, r);
+    IntegCtl &c = *p->host;
+    memset(&c, 0, sizeof(c));
+    c.U = I.Ut;
+    c.V = I.Vt;
+    c.lam = lambda;
+    c.t_end = 1e300;
+    c.max_steps = 100000000LL;
+    smol_options o{};
+    ctl_setup(c, method, o, 1e-6, 1e-12);
+    HIP_TRY(hipMemcpyAsync(p->ctl, &c, sizeof(c), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, U, I.Ut, M, R, M, I.Mt, p->logL);
+    hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, V, I.Vt, M, R, M, I.Mt, p->logL);
+    hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, n0, I.nb[0], M, 1, M, I.Mt, p->logL);
+    const int S = k_scheme_stages[method];
+    const int nC = p->dC.jobs;
+    if ((rc = launch_stage(p, I, method, 0, 0, s))) return rc;
+    hipLaunchKernelGGL(k_init_h0, dim3(1), dim3(SMOL_WG), 0, s, I, nC);
+    if ((rc = launch_stage(p, I, method, 1, 0, s))) return rc;
+    hipLaunchKernelGGL(k_init_h, dim3(1), dim3(SMOL_WG), 0, s, I, nC);
+    for (int st = 2; st <= S && !rc; ++st) rc = launch_stage(p, I, method, st, S, s);
+    if (rc) return rc;
+    HIP_TRY(hipGetLastError());
+    hipEvent_t ev[5];
+    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+    HIP_TRY(hipEventRecord(ev[0], s));
+    for (int i = 0; i < iters && !rc; ++i)
+        rc = launch_int_A(p->logL, SMOL_FP64, p->var[0], I, 2, method, s);
+    HIP_TRY(hipEventRecord(ev[1], s));
+    for (int i = 0; i < iters && !rc; ++i)
+        rc = launch_int_B(p->logL, SMOL_FP64, p->var[1], I, 3, p->dA.jobs, nC, s);
+    HIP_TRY(hipEventRecord(ev[2], s));
+    for (int i = 0; i < iters && !rc; ++i)
+        rc = launch_int_C(p->logL, SMOL_FP64, p->var[2], true, I, 3, method, s);
+    HIP_TRY(hipEventRecord(ev[3], s));
+    for (int i = 0; i < iters && !rc; ++i)
+        rc = launch_int_C(p->logL, SMOL_FP64, p->var[2], false, I, S, method, s);
+    HIP_TRY(hipEventRecord(ev[4], s));
+    HIP_TRY(hipEventSynchronize(ev[4]));
+    if (rc) return rc;
+    HIP_TRY(hipGetLastError());
+    for (int k = 0; k < 4; ++k) {
+        float t;
+        HIP_TRY(hipEventElapsedTime(&t, ev[k], ev[k + 1]));
+        ms_out[k] = t / (float)iters;
+    }
+    for (auto &e : ev) HIP_TRY(hipEventDestroy(e));
+    return SMOL_OK;
+}
+
 
 // --------------------------------------------------------------------------
 // Launch schedules and the autotuner

@@ -118,3 +118,26 @@ def test_autotune(smol, restore):
     idx = np.array([0, 1, 500, M - 1])
     ref = oracle.rhs_entries(U, V, 0.005, n, idx)
     assert np.abs(got[idx] - ref).max() / np.abs(got).max() < TOL_RHS
+
+
+@pytest.mark.parametrize("method", ["bs3", "dp5"])
+def test_profile_step_times_and_leaves_inputs(smol, method):
+    """The stage-kernel timing hook returns positive times, does not touch
+    the caller's arrays, and a later integration is unaffected."""
+    import torch
+    M = 5000
+    U, V = W.brownian_rank3(M, 0.4)
+    n0 = W.exponential_start(M, 10.0)
+    Ud, Vd, nd = t(U), t(V), t(n0)
+    before = nd.clone()
+    ref, st_ref = smol.integrate(Ud, Vd, 0.01, nd, 2.0, 1e-6, 1e-12, method="dp5")
+    ref = ref.cpu().numpy()
+    ms = smol.profile_step(Ud, Vd, 0.01, nd, method=method, iters=5)
+    torch.cuda.synchronize()
+    say(f"profile_step {method} M={M}: {ms}")
+    assert set(ms) == {"int_a", "int_b", "int_c_fused", "int_c_last"}
+    assert all(np.isfinite(v) and v > 0 for v in ms.values())
+    assert torch.equal(nd, before)
+    out, st = smol.integrate(Ud, Vd, 0.01, nd, 2.0, 1e-6, 1e-12, method="dp5")
+    assert st["n_accept"] == st_ref["n_accept"] and st["n_reject"] == st_ref["n_reject"]
+    assert np.array_equal(out.cpu().numpy(), ref)
