@@ -44,11 +44,11 @@ enum {
  * Runge--Kutta--Fehlberg 4(5) propagating the fourth-order solution, with
  * the fifth-order one for the error estimate; SMOL_RK2_DBL is RK2 (Heun)
  * with step doubling: each attempt takes one step h and two steps h/2,
- * propagates the latter, and estimates the error by their difference.
- * Each attempt also evaluates S at its new state, which is the next
- * attempt's first stage (so a rejected attempt costs one evaluation more
- * than the scheme itself needs).  SMOL_RK4_DBL (RK4 with step doubling)
- * needs 12 stage vectors and is not provided: SMOL_EUNSUPPORTED. */
+ * propagates the latter, and estimates the error by their difference;
+ * SMOL_RK4_DBL is the same with the classical four-stage RK4 (eleven
+ * evaluations per attempt).  Each attempt also evaluates S at its new
+ * state, which is the next attempt's first stage (so a rejected attempt
+ * costs one evaluation more than the scheme itself needs). */
 enum { SMOL_BS32 = 0, SMOL_DP54 = 1, SMOL_RKF45 = 2, SMOL_RK2_DBL = 3, SMOL_RK4_DBL = 4 };
 
 /* Arithmetic of the convolution part of the right-hand side. */

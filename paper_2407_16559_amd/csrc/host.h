@@ -42,16 +42,14 @@ inline int fft_log2(int64_t M)
 }
 
 // Stages (with the stage evaluated at the new state) and error-estimate
-// order q of each scheme, indexed by SMOL_BS32 .. SMOL_RK2_DBL.
-static const int k_scheme_stages[4] = {4, 7, 7, 6};
-static const int k_scheme_q[4] = {2, 4, 4, 2};
+// order q of each scheme, indexed by SMOL_BS32 .. SMOL_RK4_DBL.
+static const int k_scheme_stages[5] = {4, 7, 7, 6, 12};
+static const int k_scheme_q[5] = {2, 4, 4, 2, 4};
 
-// SMOL_OK for a scheme this build runs, SMOL_EUNSUPPORTED for a known one it
-// does not, SMOL_EINVAL otherwise.
+// SMOL_OK for a known scheme, SMOL_EINVAL otherwise.
 inline int check_method(int32_t method)
 {
-    if (method >= SMOL_BS32 && method <= SMOL_RK2_DBL) return SMOL_OK;
-    return method == SMOL_RK4_DBL ? SMOL_EUNSUPPORTED : SMOL_EINVAL;
+    return (method >= SMOL_BS32 && method <= SMOL_RK4_DBL) ? SMOL_OK : SMOL_EINVAL;
 }
 inline bool controller_valid(int32_t c) { return c >= SMOL_CTRL_PI && c <= SMOL_CTRL_HALVE_DOUBLE; }
 

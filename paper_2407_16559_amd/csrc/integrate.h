@@ -31,6 +31,8 @@ struct Tableau {
     int q;             // order of the embedded solution
     double a[8][8];    // a[i][j], 0-based
     double d[8];       // b_j - bhat_j
+    int fsal;          // stage slot paired with slot 0 (k_1 / k_S swap on accept)
+    int program;       // 1: stages 3..S follow the RK4 step-doubling program
 };
 
 // Bogacki & Shampine (1989) 3(2), Dormand & Prince (1980) 5(4), and two of
@@ -43,10 +45,11 @@ struct Tableau {
 //   (n + h k1), stages 3-5 the two half steps (n + h/2 k1; the midpoint
 //   n + h/4 (k1 + k3); its half step n + h (k1/4 + k3/4 + k4/2)), stage 6 the
 //   two-half-step solution nhat (propagated); d = nhat - single step.
-__constant__ Tableau c_tab[4] = {
+__constant__ Tableau c_tab[5] = {
     {4, 2,
      {{0}, {1.0 / 2}, {0.0, 3.0 / 4}, {2.0 / 9, 1.0 / 3, 4.0 / 9}},
-     {2.0 / 9 - 7.0 / 24, 1.0 / 3 - 1.0 / 4, 4.0 / 9 - 1.0 / 3, -1.0 / 8}},
+     {2.0 / 9 - 7.0 / 24, 1.0 / 3 - 1.0 / 4, 4.0 / 9 - 1.0 / 3, -1.0 / 8},
+     3},
     {7, 4,
      {{0},
       {1.0 / 5},
@@ -56,7 +59,8 @@ __constant__ Tableau c_tab[4] = {
       {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656},
       {35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}},
      {35.0 / 384 - 5179.0 / 57600, 0.0, 500.0 / 1113 - 7571.0 / 16695, 125.0 / 192 - 393.0 / 640,
-      -2187.0 / 6784 + 92097.0 / 339200, 11.0 / 84 - 187.0 / 2100, -1.0 / 40}},
+      -2187.0 / 6784 + 92097.0 / 339200, 11.0 / 84 - 187.0 / 2100, -1.0 / 40},
+     6},
     {7, 4,
      {{0},
       {1.0 / 4},
@@ -66,7 +70,8 @@ __constant__ Tableau c_tab[4] = {
       {-8.0 / 27, 2.0, -3544.0 / 2565, 1859.0 / 4104, -11.0 / 40},
       {25.0 / 216, 0.0, 1408.0 / 2565, 2197.0 / 4104, -1.0 / 5, 0.0}},
      {25.0 / 216 - 16.0 / 135, 0.0, 1408.0 / 2565 - 6656.0 / 12825,
-      2197.0 / 4104 - 28561.0 / 56430, -1.0 / 5 + 9.0 / 50, -2.0 / 55, 0.0}},
+      2197.0 / 4104 - 28561.0 / 56430, -1.0 / 5 + 9.0 / 50, -2.0 / 55, 0.0},
+     6},
     {6, 2,
      {{0},
       {1.0},
@@ -74,7 +79,12 @@ __constant__ Tableau c_tab[4] = {
       {1.0 / 4, 0.0, 1.0 / 4},
       {1.0 / 4, 0.0, 1.0 / 4, 1.0 / 2},
       {1.0 / 4, 0.0, 1.0 / 4, 1.0 / 4, 1.0 / 4}},
-     {1.0 / 4 - 1.0 / 2, -1.0 / 2, 1.0 / 4, 1.0 / 4, 1.0 / 4, 0.0}},
+     {1.0 / 4 - 1.0 / 2, -1.0 / 2, 1.0 / 4, 1.0 / 4, 1.0 / 4, 0.0},
+     5},
+    // RK4 with step doubling: twelve stages whose combinations do not fit a
+    // tableau of this size; only a_21 (the single step's k_2 at n + h/2 k_1)
+    // is read from here, the rest is the stage program of rk4d_epi.
+    {12, 4, {{0}, {1.0 / 2}}, {0}, 5, 1},
 };
 
 struct IntegCtl {
@@ -168,10 +178,10 @@ __device__ __forceinline__ RhsPlanDev plan_of_ws(const IntegDev &I)
 }
 
 // stage j (1-based) vector given the FSAL parity kp
-__device__ __forceinline__ double *kvec(const IntegDev &I, const IntegCtl &c, int S, int j)
+__device__ __forceinline__ double *kvec(const IntegDev &I, const IntegCtl &c, const Tableau &T, int j)
 {
-    if (j == 1) return I.kslot[c.kp ? S - 1 : 0];
-    if (j == S) return I.kslot[c.kp ? 0 : S - 1];
+    if (j == 1) return I.kslot[c.kp ? T.fsal : 0];
+    if (j == T.S) return I.kslot[c.kp ? 0 : T.fsal];
     return I.kslot[j - 1];
 }
 
@@ -182,14 +192,103 @@ __device__ __forceinline__ Pro stage_pro(const IntegDev &I, const IntegCtl &c, c
     const int S = T.S;
     double *n = I.nb[c.cur];
     if (stage == 0) return Pro{A_COMBINE, n, nullptr, 0.0, nullptr};
-    if (stage == 1) return Pro{A_COMBINE, n, kvec(I, c, S, 1), c.h0, I.ybuf};
-    if (stage == 2) return Pro{A_COMBINE, n, kvec(I, c, S, 1), c.h * T.a[1][0], I.ybuf};
+    if (stage == 1) return Pro{A_COMBINE, n, kvec(I, c, T, 1), c.h0, I.ybuf};
+    if (stage == 2) return Pro{A_COMBINE, n, kvec(I, c, T, 1), c.h * T.a[1][0], I.ybuf};
     return Pro{A_GIVEN, stage == S ? I.nb[c.cur ^ 1] : I.ybuf, nullptr, 0.0, nullptr};
+}
+
+// RK4 with step doubling (Sec. 2: one classical RK4 step of size h and two
+// of size h/2 from the same state, the two half steps propagated, the error
+// their difference) as a twelve-stage program on the stage machinery:
+//   stages 2-4   the single step: k_2 = S(n + h/2 k_1), k_3 = S(n + h/2 k_2),
+//                k_4 = S(n + h k_3);
+//   stages 5-7   the first half step: k_5 = S(n + h/4 k_1),
+//                k_6 = S(n + h/4 k_5), k_7 = S(n + h/2 k_6), ending on the
+//                midpoint m = n + h/12 (k_1 + 2 k_5 + 2 k_6 + k_7);
+//   stages 8-11  the second half step from m: k_8 = S(m),
+//                k_9 = S(m + h/4 k_8), k_10 = S(m + h/4 k_9),
+//                k_11 = S(m + h/2 k_10), nhat = m + h/12 (k_8 + 2 k_9 + 2 k_10 + k_11);
+//   stage 12     k_12 = S(nhat), the next attempt's k_1, with the error
+//                nhat - n_single = (nhat - n) + h D.
+// Stage 4 stores D = -(k_1 + 2 k_2 + 2 k_3 + k_4) / 6 in place of k_4 (the
+// single step is needed only through D), so seven slots suffice:
+//   slot 0 / fsal  k_1 and k_12 (k_11 is written where k_12 will go);
+//   1: k_2, k_5, k_8;  2: k_3, k_6, k_9;  3: D;  4: k_7, k_10;  6: m.
+__device__ inline Epi rk4d_epi(const IntegDev &I, const IntegCtl &c, const Tableau &T, int stage)
+{
+    Epi ep{};
+    ep.n = I.nb[c.cur];
+    ep.h = c.h;
+    ep.rtol = c.rtol;
+    ep.atol = c.atol;
+    ep.epart = I.epart;
+    ep.mode = C_STAGE;
+    ep.y = I.ybuf;
+    ep.ynext = I.ybuf;
+    double *k1 = kvec(I, c, T, 1), *k12 = kvec(I, c, T, T.S), *m = I.kslot[6];
+    switch (stage) {
+    case 2: ep.out = I.kslot[1]; ep.cS = 1.0 / 2; break;
+    case 3: ep.out = I.kslot[2]; ep.cS = 1.0; break;
+    case 4:
+        ep.out = I.kslot[3];
+        ep.ks[0] = k1;
+        ep.ks[1] = I.kslot[1];
+        ep.ks[2] = I.kslot[2];
+        ep.coef[0] = 1.0 / 4;
+        ep.nks = 3;
+        ep.ocomb = 1;
+        ep.oS = -1.0 / 6;
+        ep.ocoef[0] = -1.0 / 6;
+        ep.ocoef[1] = -1.0 / 3;
+        ep.ocoef[2] = -1.0 / 3;
+        break;
+    case 5: ep.out = I.kslot[1]; ep.cS = 1.0 / 4; break;
+    case 6: ep.out = I.kslot[2]; ep.cS = 1.0 / 2; break;
+    case 7:
+        ep.out = I.kslot[4];
+        ep.ynext = m;
+        ep.ks[0] = k1;
+        ep.ks[1] = I.kslot[1];
+        ep.ks[2] = I.kslot[2];
+        ep.coef[0] = 1.0 / 12;
+        ep.coef[1] = 1.0 / 6;
+        ep.coef[2] = 1.0 / 6;
+        ep.cS = 1.0 / 12;
+        ep.nks = 3;
+        break;
+    case 8: ep.y = m; ep.n = m; ep.out = I.kslot[1]; ep.cS = 1.0 / 4; break;
+    case 9: ep.n = m; ep.out = I.kslot[2]; ep.cS = 1.0 / 4; break;
+    case 10: ep.n = m; ep.out = I.kslot[4]; ep.cS = 1.0 / 2; break;
+    case 11:
+        ep.n = m;
+        ep.out = k12;
+        ep.ynext = I.nb[c.cur ^ 1];
+        ep.ks[0] = I.kslot[1];
+        ep.ks[1] = I.kslot[2];
+        ep.ks[2] = I.kslot[4];
+        ep.coef[0] = 1.0 / 12;
+        ep.coef[1] = 1.0 / 6;
+        ep.coef[2] = 1.0 / 6;
+        ep.cS = 1.0 / 12;
+        ep.nks = 3;
+        break;
+    default:  // stage 12
+        ep.mode = C_LAST;
+        ep.y = I.nb[c.cur ^ 1];
+        ep.out = k12;
+        ep.ks[0] = I.kslot[3];
+        ep.coef[0] = 1.0;
+        ep.nks = 1;
+        ep.diff = 1;
+        break;
+    }
+    return ep;
 }
 
 __device__ inline Epi stage_epi(const IntegDev &I, const IntegCtl &c, const Tableau &T, int stage)
 {
     const int S = T.S;
+    if (T.program && stage >= 2) return rk4d_epi(I, c, T, stage);
     Epi ep{};
     ep.n = I.nb[c.cur];
     ep.h = c.h;
@@ -199,22 +298,22 @@ __device__ inline Epi stage_epi(const IntegDev &I, const IntegCtl &c, const Tabl
     if (stage == 0) {
         ep.mode = C_INIT0;
         ep.y = ep.n;
-        ep.out = kvec(I, c, S, 1);
+        ep.out = kvec(I, c, T, 1);
     } else if (stage == 1) {
         ep.mode = C_INIT1;
         ep.y = I.ybuf;
-        ep.ks[0] = kvec(I, c, S, 1);
+        ep.ks[0] = kvec(I, c, T, 1);
         ep.coef[0] = 1.0;  // marks the slot as used: f0
         ep.nks = 1;
     } else if (stage < S) {
         // fixed slots j-1 for k_j (zero coefficients are skipped at use)
         ep.mode = C_STAGE;
         ep.y = I.ybuf;
-        ep.out = kvec(I, c, S, stage);
+        ep.out = kvec(I, c, T, stage);
         ep.ynext = (stage + 1 == S) ? I.nb[c.cur ^ 1] : I.ybuf;
 #pragma unroll
         for (int j = 1; j < SMOL_MAX_STAGE; ++j) {
-            ep.ks[j - 1] = kvec(I, c, S, j < S ? j : 1);
+            ep.ks[j - 1] = kvec(I, c, T, j < S ? j : 1);
             ep.coef[j - 1] = j < stage ? T.a[stage][j - 1] : 0.0;
         }
         ep.nks = stage - 1;
@@ -222,10 +321,10 @@ __device__ inline Epi stage_epi(const IntegDev &I, const IntegCtl &c, const Tabl
     } else {
         ep.mode = C_LAST;
         ep.y = I.nb[c.cur ^ 1];
-        ep.out = kvec(I, c, S, S);
+        ep.out = kvec(I, c, T, S);
 #pragma unroll
         for (int j = 1; j < SMOL_MAX_STAGE; ++j) {
-            ep.ks[j - 1] = kvec(I, c, S, j < S ? j : 1);
+            ep.ks[j - 1] = kvec(I, c, T, j < S ? j : 1);
             ep.coef[j - 1] = j < S ? T.d[j - 1] : 0.0;
         }
         ep.nks = S - 1;

@@ -99,6 +99,11 @@ struct Epi {
     double *ynext;          // C_STAGE: next stage state
     double rtol, atol;
     double *epart;          // C_LAST / C_INIT*: [jobs][SMOL_EPART]
+    // C_STAGE with ocomb: out receives oS S + sum_j ocoef[j] ks[j] instead of S
+    int ocomb;
+    double oS;
+    double ocoef[SMOL_MAX_STAGE];
+    int diff;               // C_LAST: the error estimate also adds y - n
 };
 
 // Sum per-wave values sh[w][0..nq) over the W waves in order (after a barrier).
@@ -423,7 +428,9 @@ struct PhaseC {
                     if (need_n) nv[j] = ep.n[q];
 #pragma unroll
                     for (int k = 0; k < KMAX; ++k)
-                        kv[j][k] = (k < nk && ep.coef[k] != 0.0) ? ep.ks[k][q] : 0.0;
+                        kv[j][k] = (k < nk && (ep.coef[k] != 0.0 || ep.ocoef[k] != 0.0))
+                                       ? ep.ks[k][q]
+                                       : 0.0;
 #pragma unroll
                     for (int a = 0; a < RPRE; ++a) {
                         if (a < rp) {
@@ -449,7 +456,7 @@ struct PhaseC {
             if (need_n) n1v = ep.n[0];
 #pragma unroll
             for (int k = 0; k < KMAX; ++k)
-                if (k < nk && ep.coef[k] != 0.0) k1v[k] = ep.ks[k][0];
+                if (k < nk && (ep.coef[k] != 0.0 || ep.ocoef[k] != 0.0)) k1v[k] = ep.ks[k][0];
             double d1 = 0.0, g1 = 0.0, pairs = 0.0;
             for (int al = 0; al < R; ++al) {
                 const double wv = P.red[4 * al], t = P.red[4 * al + 1];
@@ -678,7 +685,15 @@ struct PhaseC {
             ep.out[q] = S;
             return 0.0;
         case C_STAGE: {
-            ep.out[q] = S;
+            if (ep.ocomb) {
+                double o = ep.oS * S;
+#pragma unroll
+                for (int j = 0; j < KMAX; ++j)
+                    if (j < nk) o = fma(ep.ocoef[j], k[j], o);
+                ep.out[q] = o;
+            } else {
+                ep.out[q] = S;
+            }
             double a = ep.cS * S;
 #pragma unroll
             for (int j = 0; j < KMAX; ++j)
@@ -694,6 +709,7 @@ struct PhaseC {
             for (int j = 0; j < KMAX; ++j)
                 if (j < nk) e = fma(ep.coef[j], k[j], e);
             e *= ep.h;
+            if (ep.diff) e += y - n;
             const double sc = fma(ep.rtol, fmax(fabs(n), fabs(y)), ep.atol);
             const double r = e / sc;
             acc[0] = fma(r, r, acc[0]);

@@ -66,7 +66,7 @@ struct Plan {
     IntegCtl *ctl = nullptr;       // device control block
     IntegCtl *host = nullptr;      // pinned mirror
     hipStream_t cap = nullptr;     // capture stream
-    hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};  // per scheme
+    hipGraphExec_t graph[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // per scheme
     // launch schedule: variant of kernels A, B, C and their grids
     int var[3] = {0, 0, 0};
     PhaseDims dA{}, dB{}, dC{}, dCf{};

@@ -1,6 +1,6 @@
 """The paper's own schemes on the GPU (Sec. 2): RKF45 with Fehlberg's rule,
-RK2 with step doubling and Eq. (6) or the halve / double rule, Euclidean
-norm.  Each run must take the oracle's decisions (accept / reject, step
+RK2 and RK4 with step doubling and Eq. (6) or the halve / double rule,
+Euclidean norm.  Each run must take the oracle's decisions (accept / reject, step
 sizes) and end on its state; the GPU evaluates S at every attempt's new
 state (the next attempt's first stage), so it counts one evaluation more per
 rejection than the oracle, which reuses S(n) across retries, and one for the
@@ -17,7 +17,9 @@ pytestmark = pytest.mark.gpu
 CASES = [("rkf45", "fehlberg", oracle.RKF45, oracle.RULE_FEHLBERG),
          ("rk2_dbl", "step_doubling", oracle.RK2_DBL, oracle.RULE_EQ6),
          ("rk2_dbl", "halve_double", oracle.RK2_DBL, oracle.RULE_HALVE_DOUBLE),
-         ("rkf45", "step_doubling", oracle.RKF45, oracle.RULE_EQ6)]
+         ("rkf45", "step_doubling", oracle.RKF45, oracle.RULE_EQ6),
+         ("rk4_dbl", "step_doubling", oracle.RK4_DBL, oracle.RULE_EQ6),
+         ("rk4_dbl", "halve_double", oracle.RK4_DBL, oracle.RULE_HALVE_DOUBLE)]
 
 
 @pytest.fixture(scope="module")
@@ -58,15 +60,6 @@ def test_paper_scheme_matches_oracle(smol, method, ctrl, scheme, rule, M, h0):
     assert normwise(out.cpu().numpy(), ref) < 1e-9
 
 
-def test_rk4_doubling_is_unsupported(smol):
-    M = 64
-    U, V = W.brownian_rank3(M, 0.4)
-    with pytest.raises(smol.SmolError) as e:
-        smol.integrate(t(U), t(V), 0.01, t(W.monodisperse(M)), 1.0, 1e-6, 0.0, method="rk4_dbl",
-                       controller="step_doubling")
-    assert e.value.code == smol.EUNSUPPORTED
-
-
 def test_paper_schemes_in_batch(smol):
     """Batched runs take the same paths: bitwise equal to single runs."""
     insts = []
@@ -74,7 +67,8 @@ def test_paper_schemes_in_batch(smol):
         U, V = W.brownian_rank3(M, a)
         insts.append(dict(U=t(U), V=t(V), lam=lam, n0=t(W.exponential_start(M, 4.0)), t_end=10.0,
                           rtol=1e-7, atol=0.0))
-    for method, ctrl in (("rkf45", "fehlberg"), ("rk2_dbl", "step_doubling")):
+    for method, ctrl in (("rkf45", "fehlberg"), ("rk2_dbl", "step_doubling"),
+                         ("rk4_dbl", "step_doubling")):
         outs, stats = smol.integrate_batch(insts, method=method, controller=ctrl)
         for d, o, st in zip(insts, outs, stats):
             r, rs = smol.integrate(d["U"], d["V"], d["lam"], d["n0"], 10.0, 1e-7, 0.0,
@@ -92,14 +86,14 @@ def test_rhs_counts_versus_tolerance(smol):
     n0 = t(W.monodisperse(M))
     rows = {}
     for tol in (1e-4, 1e-6, 1e-8):
-        for method, ctrl in (("rk2_dbl", "step_doubling"), ("rkf45", "fehlberg"),
-                             ("dp5", "pi")):
+        for method, ctrl in (("rk2_dbl", "step_doubling"), ("rk4_dbl", "step_doubling"),
+                             ("rkf45", "fehlberg"), ("dp5", "pi")):
             rtol, atol = (tol, 0.0) if ctrl != "pi" else (tol, tol * 1e-6)
             _, st = smol.integrate(t(U), t(V), 0.01, n0, 100.0, rtol, atol, method=method,
                                    controller=ctrl)
             assert st["status"] == 0
             rows[(method, tol)] = st["n_rhs"]
-    for method in ("rk2_dbl", "rkf45", "dp5"):
+    for method in ("rk2_dbl", "rk4_dbl", "rkf45", "dp5"):
         say(f"{method}: RHS evaluations at tol 1e-4 / 1e-6 / 1e-8: "
             f"{rows[(method, 1e-4)]} / {rows[(method, 1e-6)]} / {rows[(method, 1e-8)]}")
     assert rows[("rkf45", 1e-8)] < rows[("rk2_dbl", 1e-8)]
