@@ -146,8 +146,8 @@ __device__ __forceinline__ RhsPlanDev plan_of(const IntegDev &I, const IntegCtl 
     P.tr = 1;
     P.ustride = I.Mt;
     P.lam = c.lam;
-    P.U = c.U;
-    P.V = c.V;
+    P.U = I.Ut;
+    P.V = I.Vt;
     P.Z = I.Z;
     P.Qp = I.Qp;
     P.red_part = I.red_part;
@@ -157,13 +157,16 @@ __device__ __forceinline__ RhsPlanDev plan_of(const IntegDev &I, const IntegCtl 
     return P;
 }
 
-// The plan fields the row-pair pass uses (transform shape, workspaces,
-// roots), which do not depend on the control block.
+// The plan fields that do not depend on the control block (transform
+// shape, factors, workspaces, roots): all the row-pair pass uses, and what
+// the finish loads before it reads the control block.
 __device__ __forceinline__ RhsPlanDev plan_of_ws(const IntegDev &I)
 {
     RhsPlanDev P{};
     P.M = I.M;
     P.R = I.R;
+    P.U = I.Ut;
+    P.V = I.Vt;
     P.logL = I.logL;
     P.logN1 = split_log_n1(I.logL);
     P.logN2 = split_log_n2(I.logL);

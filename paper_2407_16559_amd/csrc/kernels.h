@@ -43,14 +43,17 @@ __global__ __launch_bounds__(64 * W) void k_phaseC(RhsPlanDev P, Epi ep, int nun
 template <int N1, int N2, class T, int E, int W>
 __global__ __launch_bounds__(64 * W) void k_int_A(IntegDev I, int stage, int nunits, int method)
 {
+    using PA = PhaseA<N1, N2, T, E, W>;
+    extern __shared__ cd lds[];
+    const int unit = xcd_remap(blockIdx.x, gridDim.x);
+    typename PA::Early e;  // twiddles and factors: requested before the control block
+    if (unit < nunits) PA::early(plan_of_ws(I), unit, e);
     const IntegCtl c = *I.ctl;  // one snapshot: all fields load together
     if (c.done) return;
-    extern __shared__ cd lds[];
     const Tableau &tab = c_tab[method];
     const RhsPlanDev P = plan_of(I, c);
     const Pro in = stage_pro(I, c, tab, stage);
-    const int unit = xcd_remap(blockIdx.x, gridDim.x);
-    if (unit < nunits) PhaseA<N1, N2, T, E, W>::run(P, in, unit, (T *)lds);
+    if (unit < nunits) PA::run_with(P, in, unit, (T *)lds, e);
 }
 
 // jobs_a / jobs_c: reduction partial rows written by the column pass (stages
@@ -72,17 +75,23 @@ __global__ __launch_bounds__(64 * W) void k_int_B(IntegDev I, int stage, int job
     PhaseB<N1, N2, T, E, W>::run(P, u, (T *)lds);
 }
 
+// The packed columns, twiddles and column-pass factors do not depend on the
+// control block, so they are requested before it and their round trips
+// overlap.
 template <int N1, int N2, class T, int E, int W, bool FUSE>
 __global__ __launch_bounds__(64 * W) void k_int_C(IntegDev I, int stage, int nunits, int method)
 {
+    using PC = PhaseC<N1, N2, T, E, W>;
+    extern __shared__ cd lds[];
+    const int unit = xcd_remap(blockIdx.x, gridDim.x);
+    typename PC::Early e;
+    if (unit < nunits) PC::template early<FUSE>(plan_of_ws(I), unit, e);
     const IntegCtl c = *I.ctl;  // one snapshot: all fields load together
     if (c.done) return;
-    extern __shared__ cd lds[];
     const Tableau &tab = c_tab[method];
     const RhsPlanDev P = plan_of(I, c);
     const Epi ep = stage_epi(I, c, tab, stage);
-    const int unit = xcd_remap(blockIdx.x, gridDim.x);
-    if (unit < nunits) PhaseC<N1, N2, T, E, W>::template run<FUSE>(P, ep, unit, (T *)lds);
+    if (unit < nunits) PC::template run_with<FUSE>(P, ep, unit, (T *)lds, e);
 }
 
 // ---- batched stage kernels: blocks [base, base + gridDim) of one shape -------

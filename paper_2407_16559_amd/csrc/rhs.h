@@ -149,8 +149,48 @@ struct PhaseA {
     static __host__ __device__ int units(int R) { return R * NG; }
     static __host__ __device__ int red_jobs() { return NG; }
 
+    static constexpr int H = F::E / 2;
+    // Loads that need only the transform shape and the factors: twiddles and
+    // this lane's U, V values (the integrator issues them before its
+    // control-block load).
+    struct Early {
+        FftTw<N1, false, C, E> tw;
+        C t4[F::E];
+        double u0[H], x0[H];
+    };
+    __device__ static void early(const RhsPlanDev &P, int unit, Early &e)
+    {
+        const int lane = lane_id(), w = wave_id();
+        const int f = lane / F::G, g = lane % F::G;
+        const int al = unit / NG, grp = unit % NG;
+        const int n2 = grp * GA + w * COLS + f;
+        const bool active = (w < WUSED) && (f < COLS);
+        const double *Ua = P.U + (int64_t)al * P.ustride, *Va = P.V + (int64_t)al * P.ustride;
+        if (active) {
+            e.tw.load(g, P.rt);
+            step_twiddles<F::E, false>(P.rt, P.logL, (uint32_t)n2, g, F::G, e.t4);
+        }
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            e.u0[i] = e.x0[i] = 0.0;
+            const int64_t idx = (int64_t)(g + i * F::G) * N2 + n2;
+            if (active && idx < P.M) {
+                const int64_t q = pos_of(P, idx);
+                e.u0[i] = Ua[q];
+                e.x0[i] = Va[q];
+            }
+        }
+    }
+
     // one unit = (rank al, group of GA columns); whole workgroup
     __device__ static void run(const RhsPlanDev &P, const Pro &in, int unit, C *lds)
+    {
+        Early e;
+        early(P, unit, e);
+        run_with(P, in, unit, lds, e);
+    }
+
+    __device__ static void run_with(const RhsPlanDev &P, const Pro &in, int unit, C *lds, Early &e)
     {
         __shared__ double sh[W * 4];
         const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
@@ -160,29 +200,24 @@ struct PhaseA {
         const bool active = (w < WUSED) && (f < COLS);
         const int64_t M = P.M;
         const double *Ua = P.U + (int64_t)al * P.ustride, *Va = P.V + (int64_t)al * P.ustride;
-        FftTw<N1, false, C, E> tw;
-        C t4[F::E];
-        if (active) {
-            tw.load(g, P.rt);
-            step_twiddles<F::E, false>(P.rt, P.logL, (uint32_t)n2, g, F::G, t4);
-        }
+        const FftTw<N1, false, C, E> &tw = e.tw;
+        const C(&t4)[F::E] = e.t4;
+        const double(&u0)[H] = e.u0;
+        const double(&x0)[H] = e.x0;
         C v[F::E];
         double sw = 0, st = 0, sr = 0, sp = 0;
         const bool comb = in.mode == A_COMBINE;
         // every load first (the y store below could alias them, which would
         // otherwise serialise one memory round trip per element)
-        constexpr int H = F::E / 2;
-        double y0[H], k0[H], u0[H], x0[H];
+        double y0[H], k0[H];
 #pragma unroll
         for (int i = 0; i < H; ++i) {
-            y0[i] = k0[i] = u0[i] = x0[i] = 0.0;
+            y0[i] = k0[i] = 0.0;
             const int64_t idx = (int64_t)(g + i * F::G) * N2 + n2;
             if (active && idx < M) {
                 const int64_t q = pos_of(P, idx);
                 y0[i] = in.y[q];
                 if (comb && in.kc) k0[i] = in.kc[q];
-                u0[i] = Ua[q];
-                x0[i] = Va[q];
             }
         }
 #pragma unroll
@@ -394,8 +429,19 @@ struct PhaseC {
     // 2 COLS columns ac+1 and ac+1+N2/2 of the next column pass (the last
     // unit also owns column 0: it computes size 1 and wraps onto row b+1),
     // so the workgroup runs that pass itself and writes the next spectra.
+    struct ColPre;
+    struct Early;
+
     template <bool FUSE = false>
     __device__ static void run(const RhsPlanDev &P, const Epi &ep, int unit, C *lds)
+    {
+        Early e;
+        early<FUSE>(P, unit, e);
+        run_with<FUSE>(P, ep, unit, lds, e);
+    }
+
+    template <bool FUSE>
+    __device__ static void run_with(const RhsPlanDev &P, const Epi &ep, int unit, C *lds, Early &e)
     {
         __shared__ double sh[W * 16];
         const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
@@ -470,24 +516,12 @@ struct PhaseC {
             S1 = -y1 * d1 + 0.5 * lam * pairs + lam * y1 * g1;
             if (P.src) S1 += P.src[0];
         }
-        // ---- inputs of this wave slot's first column-pass transform
-        ColPre pre;
-        if constexpr (FUSE) {
-            const int job = w * F::B + lane / F::G;
-            if (job < 2 * COLS * R) col_load(P, unit, job, pre);
-        }
+        ColPre &pre = e.pre;
         // ---- inverse DFT over k1 of this unit's packed columns (wave 0)
         if (w == 0) {
             const int f = lane / F::G, g = lane % F::G;
-            const int ac = unit * COLS + f;
-            FftTw<N1, true, C, E> tw;
-            tw.load(g, P.rt);
-            C v[F::E];
-            const C *Qp = (const C *)P.Qp;
-#pragma unroll
-            for (int i = 0; i < F::E; ++i)
-                v[i] = f < COLS ? Qp[(int64_t)(g + i * F::G) * HALF + ac] : czero<C>();
-            wave_fft<N1, true>(v, lds + f * N1, g, tw);
+            C(&v)[F::E] = e.v;
+            wave_fft<N1, true>(v, lds + f * N1, g, e.tw);
             wave_sync();
             if (f < COLS) {
 #pragma unroll
@@ -612,6 +646,12 @@ struct PhaseC {
         C t4[F::E];
         double u[F::E / 2], x[F::E / 2];
     };
+    struct Early {
+        FftTw<N1, true, C, E> tw;  // wave 0: inverse twiddles
+        C v[F::E];                 // wave 0: the unit's packed columns
+        ColPre pre;                // FUSE: this wave slot's first column-pass transform
+    };
+
     __device__ static void col_job(const RhsPlanDev &P, int unit, int job, int &jj, int &al, int &n2)
     {
         jj = job % (2 * COLS);
@@ -638,6 +678,29 @@ struct PhaseC {
                 pre.u[i] = Ua[q];
                 pre.x[i] = Va[q];
             }
+        }
+    }
+
+    // Loads that need only the transform shape and workspaces: wave 0's
+    // packed columns of the inverse pass with their twiddles, and (fused)
+    // the factors and twiddles of each wave slot's first column-pass
+    // transform.  The integrator issues them before its control-block load.
+    template <bool FUSE>
+    __device__ static void early(const RhsPlanDev &P, int unit, Early &e)
+    {
+        const int lane = lane_id(), w = wave_id();
+        if constexpr (FUSE) {
+            const int job = w * F::B + lane / F::G;
+            if (job < 2 * COLS * P.R) col_load(P, unit, job, e.pre);
+        }
+        if (w == 0) {
+            const int f = lane / F::G, g = lane % F::G;
+            const int ac = unit * COLS + f;
+            e.tw.load(g, P.rt);
+            const C *Qp = (const C *)P.Qp;
+#pragma unroll
+            for (int i = 0; i < F::E; ++i)
+                e.v[i] = f < COLS ? Qp[(int64_t)(g + i * F::G) * HALF + ac] : czero<C>();
         }
     }
 
