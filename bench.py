@@ -26,7 +26,7 @@ HBM_PEAK = 8.0e12
 # profiles/ are used only while these files are unchanged
 KERNEL_SOURCES = ["common.h", "ff.h", "fft.h", "rhs.h", "integrate.h", "kernels.h", "sched.h",
                   "schedule_table.h", "phases_a.hip", "phases_b.hip", "phases_c.hip"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_rhs_M65536_R3.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_M65536_R3.md")
 
 
 def kernel_source_hash():
