@@ -130,6 +130,8 @@ def main():
                     help="skip the tight reference run that selects rtol (profiling)")
     ap.add_argument("--train-instances", type=int, default=128)
     ap.add_argument("--epochs", type=int, default=100)
+    ap.add_argument("--err-target", type=float, default=0.8,
+                    help="learned workload: error norm the hindsight training targets aim at")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -352,7 +354,7 @@ def bench_learned(args, smol, W, torch, dev):
         t_runs += time.perf_counter() - t0
         for log, st in zip(logs, stats):
             X, tg = smol.proposer_dataset(log, min(cap, st["n_accept"] + st["n_reject"]), "dp5",
-                                          0.8)
+                                          args.err_target)
             Xs.append(X)
             Ts.append(tg)
         print(f"bench: training runs {lo + len(insts)}/{len(draws)} ({t_runs:.1f} s)",
@@ -389,6 +391,7 @@ def bench_learned(args, smol, W, torch, dev):
                      "reject_rate": st["n_reject"] / max(1, st["n_accept"] + st["n_reject"]),
                      "n_fallback": st["n_fallback"], "rel_err_vs_tight_run": err}
         print(f"bench: {ctrl}: {res[ctrl]}", file=sys.stderr, flush=True)
+    sweep = bench_sweep_learned(args, smol, W, torch, dev)
     line = {
         "metric": "time-to-t_end with the learned step proposer, M=2^18 R=3",
         "value": res["learned"]["time_to_t_end_s"],
@@ -399,15 +402,71 @@ def bench_learned(args, smol, W, torch, dev):
         "dtype": "f64 (network f32)", "data": "synthetic",
         "config": {"workload": f"learned-proposer: M=262144, R=3, a=0.4, lam=0.01, monodisperse, "
                                f"DP5(4), rtol=1e-6, atol=1e-12, t_end={t_end:g}; trained on "
-                               f"{len(draws)} sweep-distributed runs", "parallelism": "1 GPU"},
+                               f"{len(draws)} sweep-distributed runs, error target "
+                               f"{args.err_target:g}", "parallelism": "1 GPU"},
         "learned": res["learned"], "pi": res["pi"],
         "speedup_vs_pi": res["pi"]["time_to_t_end_s"] / res["learned"]["time_to_t_end_s"],
         "rhs_ratio_vs_pi": res["learned"]["n_rhs"] / res["pi"]["n_rhs"],
         "training": {"runs_s": t_runs, "rows": int(X.shape[0]), "epochs": args.epochs,
                      "train_s": t_train, "loss_first": loss[0].item(),
                      "loss_last": loss[-1].item()},
+        "batched_sweep": sweep,
     }
     print(json.dumps(line), flush=True)
+
+
+def bench_sweep_learned(args, smol, W, torch, dev):
+    """The batched form with the trained proposer against the plain
+    single-instance PI solver: the 256 sweep instances of the batched
+    workload (seed 0, held out from the training seed), DP5(4) (the pair the
+    proposer was trained on), rtol 1e-6, atol 1e-12, t = 0 -> 1e3.  Batched
+    runs with the learned controller and with PI are timed whole; the
+    single-instance PI runs on every 32nd instance, extrapolated to all 256.
+    Accuracy: on those sampled instances both batched end states are
+    compared with tight single runs (rtol 1e-10, atol 1e-16)."""
+    c = W.CONFIGS[3]
+    t_end = c["t_end"]
+    draws = W.batch_draws(c["n_inst"], seed=c["seed"])
+    insts = []
+    for d in draws:
+        U, V, lam, n0 = W.batch_instance(d)
+        insts.append(dict(U=torch.from_numpy(U).to(dev), V=torch.from_numpy(V).to(dev), lam=lam,
+                          n0=torch.from_numpy(n0).to(dev), t_end=t_end, rtol=c["rtol"],
+                          atol=c["atol"]))
+    res, outs = {}, {}
+    for ctrl in ("pi", "learned"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o, stats = smol.integrate_batch(insts, method="dp5", controller=ctrl)
+        torch.cuda.synchronize()
+        outs[ctrl] = o
+        res["batched_" + ctrl] = {
+            "time_s": time.perf_counter() - t0,
+            "n_rhs": sum(st["n_rhs"] for st in stats),
+            "n_reject": sum(st["n_reject"] for st in stats),
+            "all_ok": all(st["status"] == 0 for st in stats)}
+    sample = list(range(0, len(insts), 32))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in sample:
+        d = insts[i]
+        smol.integrate(d["U"], d["V"], d["lam"], d["n0"], t_end, d["rtol"], d["atol"],
+                       method="dp5", raise_on_error=True)
+    torch.cuda.synchronize()
+    res["single_pi_extrapolated_s"] = (time.perf_counter() - t0) * len(insts) / len(sample)
+    err = {"pi": 0.0, "learned": 0.0}
+    for i in sample:
+        d = insts[i]
+        ref, _ = smol.integrate(d["U"], d["V"], d["lam"], d["n0"], t_end, 1e-10, 1e-16,
+                                method="dp5", raise_on_error=True)
+        for ctrl in err:
+            e = ((outs[ctrl][i] - ref).abs().max() / ref.abs().max()).item()
+            err[ctrl] = max(err[ctrl], e)
+    res["max_rel_err_vs_tight_on_sample"] = err
+    res["speedup_batched_learned_vs_single_pi"] = (res["single_pi_extrapolated_s"]
+                                                  / res["batched_learned"]["time_s"])
+    print(f"bench: batched sweep: {res}", file=sys.stderr, flush=True)
+    return res
 
 
 if __name__ == "__main__":

@@ -60,6 +60,35 @@ def test_paper_scheme_matches_oracle(smol, method, ctrl, scheme, rule, M, h0):
     assert normwise(out.cpu().numpy(), ref) < 1e-9
 
 
+@pytest.mark.parametrize("M", [1, 2, 3, 64])
+def test_rk4_doubling_small_sizes(smol, M):
+    """Degenerate sizes (a single size class, the smallest transforms): the
+    same decisions as the oracle and the same end state."""
+    U, V = W.brownian_rank3(M, 0.3)
+    n0 = W.exponential_start(M, 2.0)
+    ref, ost, _ = oracle.integrate_paper(U, V, 0.05, n0, 5.0, 1e-8, oracle.RK4_DBL,
+                                         oracle.RULE_EQ6)
+    out, st = smol.integrate(t(U), t(V), 0.05, t(n0), 5.0, 1e-8, 0.0, method="rk4_dbl",
+                             controller="step_doubling")
+    say(f"rk4_dbl M={M}: gpu {st['n_accept']}/{st['n_reject']}, "
+        f"oracle {ost['n_accept']}/{ost['n_reject']}")
+    assert st["status"] == 0 and (st["n_accept"], st["n_reject"]) == (ost["n_accept"], ost["n_reject"])
+    assert normwise(out.cpu().numpy(), ref) < 1e-12
+
+
+def test_rk4_doubling_closed_form(smol):
+    """K == 1, lam = 0, n(0) = e_1: n_s(t) = (t/2)^(s-1) / (1+t/2)^(s+1),
+    reached by RK4 with step doubling at a tight tolerance."""
+    M, T = 1024, 5.0
+    U, V = W.constant_kernel(M)
+    out, st = smol.integrate(t(U), t(V), 0.0, t(W.monodisperse(M)), T, 1e-11, 0.0,
+                             method="rk4_dbl", controller="step_doubling")
+    s = np.arange(1, M + 1)
+    ref = np.exp((s - 1) * np.log(T / 2) - (s + 1) * np.log1p(T / 2))
+    assert st["status"] == 0
+    assert normwise(out.cpu().numpy(), ref) < 1e-8
+
+
 def test_paper_schemes_in_batch(smol):
     """Batched runs take the same paths: bitwise equal to single runs."""
     insts = []

@@ -57,17 +57,20 @@ def test_embedded_run_with_sources(smol, method, name):
     assert normwise(out.cpu().numpy(), ref) < 1e-9
 
 
-def test_paper_scheme_with_sources(smol):
+@pytest.mark.parametrize("method,ctrl,scheme,rule",
+                         [("rkf45", "fehlberg", oracle.RKF45, oracle.RULE_FEHLBERG),
+                          ("rk4_dbl", "step_doubling", oracle.RK4_DBL, oracle.RULE_EQ6)])
+def test_paper_scheme_with_sources(smol, method, ctrl, scheme, rule):
     import torch
     M = 250
     U, V = W.brownian_rank3(M, 1.0 / 3.0)
     n0 = W.monodisperse(M)
     P = two_sources(M, 0.1)
     log = torch.zeros((5000, 9), dtype=torch.float64, device="cuda:0")
-    out, st = smol.integrate(t(U), t(V), 0.0, t(n0), 20.0, 1e-7, 0.0, method="rkf45",
-                             controller="fehlberg", log=log, source=t(P))
-    ref, rst, rlog = oracle.integrate_paper(U, V, 0.0, n0, 20.0, 1e-7, oracle.RKF45,
-                                            oracle.RULE_FEHLBERG, log_cap=5000, source=P)
+    out, st = smol.integrate(t(U), t(V), 0.0, t(n0), 20.0, 1e-7, 0.0, method=method,
+                             controller=ctrl, log=log, source=t(P))
+    ref, rst, rlog = oracle.integrate_paper(U, V, 0.0, n0, 20.0, 1e-7, scheme, rule,
+                                            log_cap=5000, source=P)
     g = log.cpu().numpy()[: len(rlog)]
     assert (st["n_accept"], st["n_reject"]) == (rst["n_accept"], rst["n_reject"])
     np.testing.assert_array_equal(g[:, 3], rlog[:, 3])
