@@ -4,14 +4,19 @@ Eq. (6) or the halve / double rule, with the Euclidean error norm.
 
 Checked against: Butcher order conditions, local error orders and the
 Richardson ratio of step doubling on the K == 1 closed form, whole runs
-against the closed form, and the worked examples the paper gives for
-Fehlberg's rule."""
+against the closed form, the worked examples the paper gives for Fehlberg's
+rule and the RKF45 coefficients it prints (both stored under tests/golden/
+with their citation)."""
+import os
+
 import numpy as np
 import pytest
 
 import oracle
 import workloads as W
 from test_oracle import _order_conditions, closed_form
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def test_rkf45_tableau_orders():
@@ -94,7 +99,8 @@ def test_fehlberg_rule_matches_worked_examples():
     r, e = _ratios(log, 40.0)
     f = lambda x: np.clip(0.9 * x ** (-0.2), 0.2, 10.0)  # noqa: E731
     np.testing.assert_allclose(r, f(e), rtol=1e-12)
-    assert abs(f(2.0) - 0.8) < 0.03 and abs(f(0.5) - 1.03) < 0.01 and abs(f(1.0) - 0.9) < 1e-15
+    for x, fac, tol in np.loadtxt(os.path.join(GOLDEN, "fehlberg_rule_examples.txt"), ndmin=2):
+        assert abs(f(x) - fac) < tol, (x, fac)
     assert st["n_reject"] > 0 and (e < 0.59).any()  # shrinking and growing both exercised
 
 
@@ -128,3 +134,26 @@ def test_rhs_counts(scheme, per_attempt):
                                       oracle.RULE_FEHLBERG)
     att = st["n_accept"] + st["n_reject"]
     assert st["n_rhs"] == 2 + per_attempt * att + st["n_accept"] - 1
+
+
+def test_rkf45_tableau_is_the_printed_one():
+    """The oracle's RKF45 coefficients are exactly the rationals the paper
+    prints (tests/golden/rkf45_sec2.txt), converted to FP64."""
+    from fractions import Fraction
+    a, b, bh = oracle.tableau(oracle.RKF45)
+    A = np.zeros((6, 6))
+    B4, B5 = np.zeros(6), np.zeros(6)
+    for line in open(os.path.join(GOLDEN, "rkf45_sec2.txt")):
+        if not line.strip() or line.startswith("#"):
+            continue
+        kind, i, j, num, den = line.split()
+        v = float(Fraction(int(num), int(den)))
+        if kind == "a":
+            A[int(i) - 1, int(j) - 1] = v
+        elif kind == "b4":
+            B4[int(j) - 1] = v
+        else:
+            B5[int(j) - 1] = v
+    np.testing.assert_array_equal(a[:6, :6], A)
+    np.testing.assert_array_equal(b[:6], B4)      # propagated: fourth order
+    np.testing.assert_array_equal(bh[:6], B5)     # error estimate: fifth order
