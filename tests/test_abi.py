@@ -49,6 +49,12 @@ def test_validation_before_device(lib):
     assert lib.smol_rhs(10, 3, p, p, 0.0, p, p, 0, None) == -1          # dndt aliases n
     assert lib.smol_rhs(10, 3, p, p, 0.0, p, ctypes.c_void_p(32), 7, None) == -1
     assert lib.smol_rhs(1 << 21, 3, p, p, 0.0, p, ctypes.c_void_p(32), 0, None) == -7
+    ms = (ctypes.c_float * 4)()
+    assert lib.smol_profile_step(0, 3, p, p, 0.0, p, 1, 5, ms, None) == -1       # M < 1
+    assert lib.smol_profile_step(64, 3, p, p, 0.0, None, 1, 5, ms, None) == -1   # no n0
+    assert lib.smol_profile_step(64, 3, p, p, 0.0, p, 1, 0, ms, None) == -1      # iters < 1
+    assert lib.smol_profile_step(64, 3, p, p, 0.0, p, 2, 5, ms, None) == -1      # not BS3 / DP5
+    assert lib.smol_profile_step(64, 3, p, p, 0.0, p, 1, 5, None, None) == -1    # no output
 
 
 def test_no_fallback_without_library(monkeypatch, tmp_path):
