@@ -134,8 +134,8 @@ def main():
                     help="learned workload: error norm the hindsight training targets aim at")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is described in DESIGN.md, not run", file=sys.stderr)
+        print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); multi-GPU "
+              "sharding is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -151,9 +151,9 @@ def main():
         return bench_learned(args, smol, W, torch, dev)
     if args.workload == "kernels":
         return bench_kernels(args, smol, W, torch, dev)
-    c = W.CONFIGS[2]
+    c = W.WORKLOADS["single-large"]
     t_end = args.t_end if args.t_end else c["t_end"]
-    U, V, lam, n0 = W.config_instance(2)
+    U, V, lam, n0 = W.workload_instance("single-large")
     M, R = U.shape[1], U.shape[0]
     Ud = torch.from_numpy(U).to(dev)
     Vd = torch.from_numpy(V).to(dev)
@@ -248,7 +248,7 @@ def bench_batch(args, smol, W, torch, dev):
     BS3, rtol 1e-6, atol 1e-12, t_end 1e3, in one batched run per bench step;
     compared with one-by-one single-instance runs of every 16th instance,
     extrapolated to all 256."""
-    c = W.CONFIGS[3]
+    c = W.WORKLOADS["batched-sweep"]
     t_end = args.t_end if args.t_end else c["t_end"]
     draws = W.batch_draws(c["n_inst"], seed=c["seed"])
     insts = []
@@ -301,7 +301,7 @@ def bench_kernels(args, smol, W, torch, dev):
     same state, then --steps copies of a 64 MiB device buffer: the reference a hardware
     byte counter is scaled by (each copy reads and writes 64 MiB)."""
     import numpy as np
-    U, V, lam, n0 = W.config_instance(2)
+    U, V, lam, n0 = W.workload_instance("single-large")
     M, R = U.shape[1], U.shape[0]
     L = 1 << int(np.ceil(np.log2(2 * M - 2)))
     Ud, Vd, nd = (torch.from_numpy(x).to(dev) for x in (U, V, W.exponential_start(M, 300.0)))
@@ -332,7 +332,7 @@ def bench_learned(args, smol, W, torch, dev):
     library's kernels.  Then one run with each controller, timed, and both
     compared with a tight run (rtol 1e-10, atol 1e-16)."""
     import numpy as np
-    c = W.CONFIGS[5]
+    c = W.WORKLOADS["learned-proposer"]
     t_end = args.t_end if args.t_end else c["t_end"]
     cap = 40000
     draws = W.batch_draws(args.train_instances, seed=1)
@@ -424,7 +424,7 @@ def bench_sweep_learned(args, smol, W, torch, dev):
     single-instance PI runs on every 32nd instance, extrapolated to all 256.
     Accuracy: on those sampled instances both batched end states are
     compared with tight single runs (rtol 1e-10, atol 1e-16)."""
-    c = W.CONFIGS[3]
+    c = W.WORKLOADS["batched-sweep"]
     t_end = c["t_end"]
     draws = W.batch_draws(c["n_inst"], seed=c["seed"])
     insts = []

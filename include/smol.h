@@ -36,7 +36,7 @@ enum {
     SMOL_ESTEPSIZE = -4,   /* step fell below max(h_min, 10 ulps of t) */
     SMOL_EMAXSTEPS = -5,   /* step-attempt limit reached */
     SMOL_ENONFINITE = -6,  /* NaN/Inf in the state or a NaN error norm */
-    SMOL_EUNSUPPORTED = -7 /* valid request this build does not provide */
+    SMOL_EUNSUPPORTED = -7 /* valid request the library does not provide */
 };
 
 /* Integration schemes.  SMOL_BS32 and SMOL_DP54 are embedded pairs
@@ -103,7 +103,8 @@ typedef struct {
  * the device; dndt must not alias n.  precision: SMOL_FP64 or SMOL_FP32X2
  * (the convolutions in float-float arithmetic, everything else FP64).
  * Asynchronous on `stream`.  Errors: SMOL_EINVAL, SMOL_ENOMEM,
- * SMOL_EDEVICE, SMOL_EUNSUPPORTED (M too large for this build).
+ * SMOL_EDEVICE, SMOL_EUNSUPPORTED (M so large that the transform would be
+ * longer than 2^20).
  */
 int smol_rhs(int64_t M, int32_t R, const double *U, const double *V,
              double lambda, const double *n, double *dndt, int32_t precision,

@@ -24,8 +24,8 @@ def smol():
 def test_config1_full_trajectory(smol):
     """Plain method, small: M = 512, rank-3 kernel a = 1/3, lam = 0.01,
     monodisperse start, BS3 with PI control, rtol 1e-6, atol 1e-12, t_end 50."""
-    c = W.CONFIGS[1]
-    U, V, lam, n0 = W.config_instance(1)
+    c = W.WORKLOADS["plain-small"]
+    U, V, lam, n0 = W.workload_instance("plain-small")
     say("config 1 trajectory")
     out, st = smol.integrate(t(U), t(V), lam, t(n0), c["t_end"], c["rtol"], c["atol"], method="bs3")
     ref, rst, _ = oracle.integrate(U, V, lam, n0, c["t_end"], c["rtol"], c["atol"],
@@ -150,7 +150,7 @@ def test_output_aliases_input(smol):
 
 def test_repeatable(smol):
     """Deterministic reductions: two runs are bitwise identical."""
-    U, V, lam, n0 = W.config_instance(1)
+    U, V, lam, n0 = W.workload_instance("plain-small")
     a, sa = smol.integrate(t(U), t(V), lam, t(n0), 20.0, 1e-6, 1e-12, method="bs3")
     b, sb = smol.integrate(t(U), t(V), lam, t(n0), 20.0, 1e-6, 1e-12, method="bs3")
     assert sa == sb and np.array_equal(a.cpu().numpy(), b.cpu().numpy())
@@ -161,8 +161,8 @@ def test_config2_full_run_properties(smol):
     oracle cannot run this trajectory, so check what holds at any size: the
     run ends at t_end, mass is conserved while the distribution stays far
     from M, and the final state's RHS matches the oracle at sampled sizes."""
-    c = W.CONFIGS[2]
-    U, V, lam, n0 = W.config_instance(2)
+    c = W.WORKLOADS["single-large"]
+    U, V, lam, n0 = W.workload_instance("single-large")
     say("config 2 full run")
     out, st = smol.integrate(t(U), t(V), lam, t(n0), c["t_end"], c["rtol"], c["atol"],
                              method="dp5")

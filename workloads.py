@@ -101,22 +101,22 @@ def random_factors(M, R, seed, lo=0.1, hi=2.0):
 # The five benchmark workloads.
 # ---------------------------------------------------------------------------
 
-CONFIGS = {
-    1: dict(name="plain-small", M=512, a=1.0 / 3.0, lam=0.01, method="bs3", rtol=1e-6,
-            atol=1e-12, t_end=50.0),
-    2: dict(name="single-large-oscillatory", M=65536, a=0.45, lam=0.005, method="dp5",
-            rtol=1e-6, atol=1e-12, t_end=1e4),
-    3: dict(name="batched-sweep", n_inst=256, method="bs3", rtol=1e-6, atol=1e-12,
-            t_end=1e3, seed=0),
-    4: dict(name="precision-fp32x2", M=65536, a=0.3, lam=0.02, t_eval=1e3),
-    5: dict(name="learned-proposer", M=262144, a=0.4, lam=0.01, method="dp5", rtol=1e-6,
-            atol=1e-12, t_end=1e4),
+WORKLOADS = {
+    "plain-small": dict(M=512, a=1.0 / 3.0, lam=0.01, method="bs3", rtol=1e-6, atol=1e-12,
+                        t_end=50.0),
+    "single-large": dict(M=65536, a=0.45, lam=0.005, method="dp5", rtol=1e-6, atol=1e-12,
+                         t_end=1e4),
+    "batched-sweep": dict(n_inst=256, method="bs3", rtol=1e-6, atol=1e-12, t_end=1e3, seed=0),
+    "precision": dict(M=65536, a=0.3, lam=0.02, t_eval=1e3),
+    "learned-proposer": dict(M=262144, a=0.4, lam=0.01, method="dp5", rtol=1e-6, atol=1e-12,
+                             t_end=1e4),
 }
 
 
-def config_instance(k):
-    """(U, V, lam, n0) of single-instance config k (1, 2 or 5)."""
-    c = CONFIGS[k]
+def workload_instance(name):
+    """(U, V, lam, n0) of a single-instance workload: rank-3 kernel
+    (i/j)^a + (j/i)^a + 2, monodisperse start."""
+    c = WORKLOADS[name]
     U, V = brownian_rank3(c["M"], c["a"])
     return U, V, c["lam"], monodisperse(c["M"])
 
