@@ -131,11 +131,12 @@ def rhs_entries(U, V, lam, n, idx, threads=0):
 
 
 def integrate(U, V, lam, n0, t_end, rtol, atol, method=DP54, h0=0.0, max_steps=0,
-              alpha=0.0, beta=-1.0, safety=0.0, facmin=0.0, facmax=0.0, threads=0,
+              alpha=0.0, beta=0.0, safety=0.0, facmin=0.0, facmax=0.0, threads=0,
               log_cap=0, h_min=0.0, source=None):
     """Adaptive embedded RK integration (optional Eq. (3) sources).  Returns
     (n_out, stats, log) where log rows are (t_start, h, err, accepted,
-    t_after) per step attempt."""
+    t_after) per step attempt.  alpha > 0 sets both PI exponents (beta of
+    either sign); otherwise both take their defaults 0.7/k and 0.4/k."""
     n0 = _f64(n0)
     U, V = _factors(U, V, n0.size)
     src = None if source is None else _f64(source)

@@ -32,7 +32,12 @@
  *       Pinned by: with beta = 0 the controller reduces to the I
  *       controller of scipy's RK23 / RK45 and must reproduce their step
  *       sequences; fixed-step convergence orders; the closed form.
- *       The beta (PI) term itself: parity unpinned.
+ *       The beta (PI) term: on the scale-invariant single-size problem
+ *       dn/dt = -K n^2 (atol = 0) the error norm of an attempt depends only
+ *       on K h n, so the controller settles where its step factor equals
+ *       the observed step growth rho; the accepted norm must then equal
+ *       (safety / rho)^(1 / (alpha - beta)).  A flipped sign of beta, or an
+ *       err_prev that is never updated, settles elsewhere and fails.
  *   oracle_rk_fixed
  *       Fixed-step version of the same tableaux (order checks), and of
  *       RKF45 as printed in Sec. 2.
@@ -292,7 +297,8 @@ typedef struct {
     double rtol, atol, t_end;
     double h0;          /* > 0: use this first step; <= 0: automatic */
     int64_t max_steps;  /* limit on step attempts; <= 0: 10^8 */
-    double alpha, beta; /* PI exponents; alpha <= 0: 0.7/k, beta < 0: 0.4/k */
+    double alpha, beta; /* PI exponents: alpha > 0 takes both as given (beta
+                           of either sign); alpha <= 0: 0.7/k and 0.4/k */
     double safety, facmin, facmax; /* <= 0: 0.9, 0.2, 10 */
     double h_min;       /* smallest allowed step (besides 10 ulps of t) */
     const double *source; /* Eq. (3) sources P_s (M doubles) or NULL */
@@ -363,7 +369,7 @@ int oracle_integrate(int64_t M, int32_t R, const double *U, const double *V,
     if (get_tableau(o->method, &T)) return OR_EINVAL;
     const int S = T.stages, k = T.q + 1;
     const double alpha = o->alpha > 0 ? o->alpha : 0.7 / k;
-    const double beta = o->beta >= 0 ? o->beta : 0.4 / k;
+    const double beta = o->alpha > 0 ? o->beta : 0.4 / k;
     const double safety = o->safety > 0 ? o->safety : 0.9;
     const double facmin = o->facmin > 0 ? o->facmin : 0.2;
     const double facmax = o->facmax > 0 ? o->facmax : 10.0;
