@@ -117,6 +117,25 @@ int smol_rhs_ex(int64_t M, int32_t R, const double *U, const double *V,
                 double lambda, const double *n, const double *source,
                 double *dndt, int32_t precision, void *stream);
 
+/* smol_rhs_noalloc -- for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): smol_rhs in FP64 (same kernels and launch schedule) whose
+ * workspaces live in one fixed device array of the library (about 9.1 MiB
+ * per GPU, held until the process ends) instead of a cached plan.  It calls
+ * no hipMalloc, hipFree or other allocating routine; its first call on a
+ * device also writes the array's unit-root tables (computed on the device,
+ * so results agree with smol_rhs to rounding, not bitwise).
+ *
+ * Limits: M <= 65537 (transform length <= 2^17) and R <= 4; larger requests
+ * return SMOL_EUNSUPPORTED.  Arguments, layout and the other errors as
+ * smol_rhs.  Asynchronous on `stream`.  Every call on a GPU uses that GPU's
+ * one array: calls that overlap in time on one GPU (different streams
+ * without ordering, or different host threads' streams) race and give
+ * wrong results; order them on one stream. */
+int smol_rhs_noalloc(int64_t M, int32_t R, const double *U, const double *V,
+                     double lambda, const double *n, double *dndt,
+                     void *stream);
+
 /*
  * smol_integrate -- integrate dn/dt = S(n), n(0) = n0 (Sec. 2, Eq. (5)) to
  * t_end with an embedded explicit Runge--Kutta pair and adaptive steps

@@ -70,6 +70,7 @@ def lib():
         i64, i32, d, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
         L.smol_rhs.argtypes = [i64, i32, vp, vp, d, vp, vp, i32, vp]
         L.smol_rhs_ex.argtypes = [i64, i32, vp, vp, d, vp, vp, vp, i32, vp]
+        L.smol_rhs_noalloc.argtypes = [i64, i32, vp, vp, d, vp, vp, vp]
         L.smol_integrate.argtypes = [i64, i32, vp, vp, d, vp, d, d, d, i32, i32, vp,
                                      ctypes.POINTER(_Stats), vp]
         L.smol_integrate_ex.argtypes = [i64, i32, vp, vp, d, vp, d, d, d, i32, i32,
@@ -163,6 +164,26 @@ def rhs(U, V, lam, n, out=None, precision="fp64", source=None):
                                    source.data_ptr(), out.data_ptr(), PRECISIONS[precision],
                                    _stream(n))
     _raise(rc, "smol_rhs")
+    return out
+
+
+NOALLOC_MAX_M, NOALLOC_MAX_R = 65537, 4
+
+
+def rhs_noalloc(U, V, lam, n, out):
+    """S(n) in FP64 with the library's fixed device workspaces (no device
+    allocation inside the call; `out` is required).  M <= 65537, R <= 4."""
+    _check(n, "n")
+    M = n.numel()
+    U, V, R = _factors(U, V, M)
+    _check(out, "out", numel=M)
+    if M > NOALLOC_MAX_M or R > NOALLOC_MAX_R:
+        raise ValueError(f"smol_rhs_noalloc serves M <= {NOALLOC_MAX_M} and R <= "
+                         f"{NOALLOC_MAX_R}; got M={M}, R={R}")
+    with torch.cuda.device(n.device):
+        rc = lib().smol_rhs_noalloc(M, R, U.data_ptr(), V.data_ptr(), float(lam), n.data_ptr(),
+                                    out.data_ptr(), _stream(n))
+    _raise(rc, "smol_rhs_noalloc")
     return out
 
 
