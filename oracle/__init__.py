@@ -65,6 +65,9 @@ def lib():
         L.oracle_rhs.argtypes = [i64, i32, P, P, d, P, P, i32]
         L.oracle_rhs_source.argtypes = [i64, i32, P, P, d, P, P, P, i32]
         L.oracle_rhs_entries.argtypes = [i64, i32, P, P, d, P, ctypes.POINTER(i64), i64, P, i32]
+        L.oracle_rhs_kernel.argtypes = [i64, i32, d, d, d, P, P, i32]
+        L.oracle_kernel_entries.argtypes = [i32, d, d, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                            i64, P]
         L.oracle_integrate.argtypes = [i64, i32, P, P, d, P, ctypes.POINTER(_Opts), P,
                                        ctypes.POINTER(_Stats), P, i64]
         L.oracle_rk_fixed.argtypes = [i64, i32, P, P, d, P, i32, d, i64, i32, P, i32]
@@ -76,6 +79,14 @@ def lib():
         L.oracle_moments.restype = None
         L.oracle_features.argtypes = [i64, P, d, P, i32, P]
         L.oracle_features.restype = None
+        L.oracle_proposer_features.argtypes = [P, d, P, i32, P]
+        L.oracle_proposer_features.restype = None
+        L.oracle_proposer_dataset.argtypes = [P, i64, i32, d, P, P]
+        L.oracle_proposer_dataset.restype = i64
+        L.oracle_learned_factor.argtypes = [P, P, d, P, i32, d, i32]
+        L.oracle_learned_factor.restype = d
+        L.oracle_learned_steps.argtypes = [P, P, i64, i32, P]
+        L.oracle_learned_steps.restype = None
         L.oracle_mlp_nparams.restype = i32
         L.oracle_mlp_forward.argtypes = [P, i64, P, P]
         L.oracle_mlp_forward.restype = None
@@ -115,6 +126,42 @@ def rhs(U, V, lam, n, threads=0):
     rc = lib().oracle_rhs(n.size, U.shape[0], _p(U), _p(V), float(lam), _p(n), _p(out), threads)
     assert rc == OK, rc
     return out
+
+
+# kernels given by a formula (Sec. 3.1)
+K_CONSTANT, K_BROWNIAN, K_FREE_MOLECULAR = 1, 2, 3
+
+
+def rhs_kernel(formula, lam, n, p0=0.0, p1=0.0, threads=0):
+    """S(n) by the direct sums with K_ij evaluated from a formula for every
+    pair (K_CONSTANT: p0; K_BROWNIAN: (i/j)^p0 + (j/i)^p0 + p1;
+    K_FREE_MOLECULAR: (i^(1/3) + j^(1/3))^2 sqrt(1/i + 1/j))."""
+    n = _f64(n)
+    out = np.empty_like(n)
+    rc = lib().oracle_rhs_kernel(n.size, int(formula), float(p0), float(p1), float(lam), _p(n),
+                                 _p(out), threads)
+    assert rc == OK, rc
+    return out
+
+
+def kernel_entries(formula, i, j, p0=0.0, p1=0.0):
+    """K_ij of a formula kernel at 1-based sizes (arrays of equal length)."""
+    i = np.ascontiguousarray(i, dtype=np.int64)
+    j = np.ascontiguousarray(j, dtype=np.int64)
+    assert i.shape == j.shape
+    out = np.empty(i.size)
+    P64 = ctypes.POINTER(ctypes.c_int64)
+    rc = lib().oracle_kernel_entries(int(formula), float(p0), float(p1), i.ctypes.data_as(P64),
+                                     j.ctypes.data_as(P64), i.size, _p(out))
+    assert rc == OK, rc
+    return out.reshape(i.shape)
+
+
+def kernel_matrix(formula, M, p0=0.0, p1=0.0):
+    """The M x M matrix K_ij (row i-1, column j-1) of a formula kernel."""
+    s = np.arange(1, M + 1, dtype=np.int64)
+    I, J = np.meshgrid(s, s, indexing="ij")
+    return kernel_entries(formula, I.ravel(), J.ravel(), p0, p1).reshape(M, M)
 
 
 def rhs_entries(U, V, lam, n, idx, threads=0):
@@ -236,6 +283,43 @@ def features(n, h, err_hist):
     x = np.zeros(9)
     lib().oracle_features(n.size, _p(n), float(h), _p(e), len(err_hist), _p(x))
     return x
+
+
+def proposer_features(mom, h, err_hist):
+    """Feature vector from the moments M0..M3 of the decision's state."""
+    mom = _f64(mom)
+    e = _f64(err_hist) if len(err_hist) else np.zeros(1)
+    x = np.zeros(9)
+    lib().oracle_proposer_features(_p(mom), float(h), _p(e), len(err_hist), _p(x))
+    return x
+
+
+def proposer_dataset(log, k, err_target=0.8):
+    """(X, target) training rows from a (rows, 9) run log (t, h, err,
+    accepted, t_after, M0..M3); k = embedded order + 1."""
+    log = _f64(log)
+    rows = log.shape[0]
+    X = np.zeros((max(rows, 1), 9))
+    tg = np.zeros(max(rows, 1))
+    n = lib().oracle_proposer_dataset(_p(log), rows, int(k), float(err_target), _p(X), _p(tg))
+    return X[:n].copy(), tg[:n].copy()
+
+
+def learned_factor(params, mom, h, err_hist, err_prev, k):
+    """h_next / h of the learned controller at one decision."""
+    params, mom = _f64(params), _f64(mom)
+    e = _f64(err_hist)
+    return lib().oracle_learned_factor(_p(params), _p(mom), float(h), _p(e), len(err_hist),
+                                       float(err_prev), int(k))
+
+
+def learned_steps(params, log, k):
+    """Per log row j: the h_{j+1}/h_j the learned controller takes at
+    decision j (NaN where the PI rule decides or there is no successor)."""
+    params, log = _f64(params), _f64(log)
+    out = np.zeros(log.shape[0])
+    lib().oracle_learned_steps(_p(params), _p(log), log.shape[0], int(k), _p(out))
+    return out
 
 
 def mlp_nparams():

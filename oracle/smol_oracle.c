@@ -41,6 +41,13 @@
  *   oracle_rk_fixed
  *       Fixed-step version of the same tableaux (order checks), and of
  *       RKF45 as printed in Sec. 2.
+ *   oracle_rhs_kernel, oracle_kernel_entries
+ *       The same direct sums with K_{ij} from a formula of Sec. 3.1
+ *       (constant, generalised Brownian, free-molecular) for every pair: the
+ *       reference for low-rank approximations of kernels with no exact
+ *       low-rank form.  Pinned by: the Brownian formula equals the exact
+ *       rank-3 factors; hand values and the degree-1/6 homogeneity of the
+ *       free-molecular kernel; the mass balance with the formula kernel.
  *   oracle_rhs_source
  *       Eq. (3): the right-hand side plus constant sources P_s (also a
  *       field of both integrators' options).  Pinned by: K == 0 gives
@@ -56,8 +63,17 @@
  *       4 and 5) and the two half steps of a doubling attempt are 2^p times
  *       closer than the single step; whole runs against the closed form at
  *       several tolerances; the step-size rules' worked examples.
- *   oracle_moments, oracle_features
+ *   oracle_moments, oracle_features, oracle_proposer_features
  *       Moments sum_s s^k n_s and the step-proposer feature vector.
+ *   oracle_proposer_dataset, oracle_learned_factor, oracle_learned_steps
+ *       The learned proposer's training rows from a run log (hindsight
+ *       target less the PI rule's log factor), the learned controller's
+ *       step factor exp(clamp(log PI + network output)), and the factors
+ *       it takes along a logged run.  Pinned by: on a
+ *       PI-controlled oracle run's log the PI part cancels exactly, leaving
+ *       (1/k) log(err_target / err_{j+1}); with err = C h^k the target step
+ *       meets err_target; a network with output b gives clamp(PI e^b), and
+ *       output 0 the oracle integrator's own PI steps.
  *   oracle_mlp_forward / oracle_mlp_loss_grad / oracle_adam
  *       The 9-64-64-1 tanh MLP step proposer, its weighted-MSE loss and
  *       gradient by backpropagation, and one Adam update, in FP64.
@@ -78,15 +94,49 @@
 #define OR_EMAXSTEPS (-5)
 #define OR_ENONFINITE (-6)
 
-/* kernel entry K_{ij} = sum_a U_{i a} V_{a j}; i, j are 1-based sizes.
- * U and V are stored alpha-major: U[a*M + i-1], V[a*M + j-1]. */
-static double kern(int64_t M, int32_t R, const double *U, const double *V,
-                   int64_t i, int64_t j)
+/* The coagulation kernel K_{ij} (i, j 1-based sizes), given either by
+ * low-rank factors (R >= 1): K_{ij} = sum_a U_{i a} V_{a j}, stored
+ * alpha-major U[a*M + i-1], V[a*M + j-1] (Sec. 1, display after Eq. (2));
+ * or (R == 0) by one of the formulas of Sec. 3.1:
+ *   ORACLE_K_CONSTANT        K = p0
+ *   ORACLE_K_BROWNIAN        K = (i/j)^p0 + (j/i)^p0 + p1 (generalised
+ *                            Brownian, exponent p0, constant term p1)
+ *   ORACLE_K_FREE_MOLECULAR  K = (i^(1/3) + j^(1/3))^2 sqrt(1/i + 1/j) */
+#define ORACLE_K_CONSTANT 1
+#define ORACLE_K_BROWNIAN 2
+#define ORACLE_K_FREE_MOLECULAR 3
+
+typedef struct {
+    int64_t M;
+    int32_t R;
+    const double *U, *V;
+    int32_t formula;
+    double p0, p1;
+} kspec;
+
+static kspec factors(int64_t M, int32_t R, const double *U, const double *V)
 {
-    double k = 0.0;
-    for (int32_t a = 0; a < R; ++a)
-        k += U[(int64_t)a * M + (i - 1)] * V[(int64_t)a * M + (j - 1)];
+    kspec k = {M, R, U, V, 0, 0.0, 0.0};
     return k;
+}
+
+static double kern(const kspec *K, int64_t i, int64_t j)
+{
+    if (K->R > 0) {
+        double k = 0.0;
+        for (int32_t a = 0; a < K->R; ++a)
+            k += K->U[(int64_t)a * K->M + (i - 1)] * K->V[(int64_t)a * K->M + (j - 1)];
+        return k;
+    }
+    const double x = (double)i, y = (double)j;
+    switch (K->formula) {
+    case ORACLE_K_CONSTANT: return K->p0;
+    case ORACLE_K_BROWNIAN: return pow(x / y, K->p0) + pow(y / x, K->p0) + K->p1;
+    default: {
+        const double c = cbrt(x) + cbrt(y);
+        return c * c * sqrt(1.0 / x + 1.0 / y);
+    }
+    }
 }
 
 static void set_threads(int32_t nthreads)
@@ -100,34 +150,34 @@ static void set_threads(int32_t nthreads)
 
 /* S_s for one 1-based size s, excluding the s = 1 double sum, which the
  * callers provide (it does not depend on s). */
-static double rhs_one(int64_t M, int32_t R, const double *U, const double *V,
-                      double lam, const double *n, int64_t s,
+static double rhs_one(const kspec *K, double lam, const double *n, int64_t s,
                       double shatter_pairs)
 {
+    const int64_t M = K->M;
     if (s == 1) {
         /* Eq. (4), first line:
          *   -n_1 sum_{i=1}^{M} K_{1,i} n_i                (aggregation loss)
          *   + (lam/2) sum_{i>=2} sum_{j>=2} (i+j) K_{ij} n_i n_j
          *   + lam n_1 sum_{j>=2} j K_{1,j} n_j             (monomer--j shattering) */
         double death = 0.0, gain = 0.0;
-        for (int64_t i = 1; i <= M; ++i) death += kern(M, R, U, V, 1, i) * n[i - 1];
-        for (int64_t j = 2; j <= M; ++j) gain += (double)j * kern(M, R, U, V, 1, j) * n[j - 1];
+        for (int64_t i = 1; i <= M; ++i) death += kern(K, 1, i) * n[i - 1];
+        for (int64_t j = 2; j <= M; ++j) gain += (double)j * kern(K, 1, j) * n[j - 1];
         return -n[0] * death + 0.5 * lam * shatter_pairs + lam * n[0] * gain;
     }
     /* Eq. (2) birth and death with Eq. (4)'s extra shattering loss, s >= 2:
      *   (1/2) sum_{i+j=s} K_{ij} n_i n_j - (1 + lam) n_s sum_{i=1}^{M} K_{s,i} n_i */
     double birth = 0.0, death = 0.0;
     for (int64_t i = 1; i <= s - 1; ++i)
-        birth += kern(M, R, U, V, i, s - i) * n[i - 1] * n[s - i - 1];
-    for (int64_t i = 1; i <= M; ++i) death += kern(M, R, U, V, s, i) * n[i - 1];
+        birth += kern(K, i, s - i) * n[i - 1] * n[s - i - 1];
+    for (int64_t i = 1; i <= M; ++i) death += kern(K, s, i) * n[i - 1];
     return 0.5 * birth - (1.0 + lam) * n[s - 1] * death;
 }
 
 /* sum_{i>=2} sum_{j>=2} (i+j) K_{ij} n_i n_j, summed row by row, rows in
  * ascending order (deterministic for any thread count). */
-static double shatter_double_sum(int64_t M, int32_t R, const double *U,
-                                 const double *V, const double *n)
+static double shatter_double_sum(const kspec *K, const double *n)
 {
+    const int64_t M = K->M;
     if (M < 2) return 0.0;
     double *row = (double *)malloc(sizeof(double) * (size_t)M);
     if (!row) return NAN;
@@ -135,7 +185,7 @@ static double shatter_double_sum(int64_t M, int32_t R, const double *U,
     for (int64_t i = 2; i <= M; ++i) {
         double acc = 0.0;
         for (int64_t j = 2; j <= M; ++j)
-            acc += (double)(i + j) * kern(M, R, U, V, i, j) * n[i - 1] * n[j - 1];
+            acc += (double)(i + j) * kern(K, i, j) * n[i - 1] * n[j - 1];
         row[i - 1] = acc;
     }
     double total = 0.0;
@@ -144,15 +194,48 @@ static double shatter_double_sum(int64_t M, int32_t R, const double *U,
     return total;
 }
 
+static void rhs_all(const kspec *K, double lam, const double *n, double *out)
+{
+    double pairs = shatter_double_sum(K, n);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t s = 1; s <= K->M; ++s)
+        out[s - 1] = rhs_one(K, lam, n, s, pairs);
+}
+
 int oracle_rhs(int64_t M, int32_t R, const double *U, const double *V,
                double lam, const double *n, double *out, int32_t nthreads)
 {
     if (M < 1 || R < 1 || !U || !V || !n || !out) return OR_EINVAL;
     set_threads(nthreads);
-    double pairs = shatter_double_sum(M, R, U, V, n);
-#pragma omp parallel for schedule(dynamic, 16)
-    for (int64_t s = 1; s <= M; ++s)
-        out[s - 1] = rhs_one(M, R, U, V, lam, n, s, pairs);
+    const kspec K = factors(M, R, U, V);
+    rhs_all(&K, lam, n, out);
+    return OR_OK;
+}
+
+/* The right-hand side with K_{ij} evaluated from a formula (see kspec) for
+ * every pair: the reference for a low-rank approximation of a kernel that
+ * has no exact low-rank form, such as the free-molecular kernel of Sec. 3.1. */
+int oracle_rhs_kernel(int64_t M, int32_t formula, double p0, double p1, double lam,
+                      const double *n, double *out, int32_t nthreads)
+{
+    if (M < 1 || !n || !out || formula < ORACLE_K_CONSTANT || formula > ORACLE_K_FREE_MOLECULAR)
+        return OR_EINVAL;
+    set_threads(nthreads);
+    const kspec K = {M, 0, NULL, NULL, formula, p0, p1};
+    rhs_all(&K, lam, n, out);
+    return OR_OK;
+}
+
+/* K_{ij} of a formula kernel for the pairs (i[q], j[q]) (1-based sizes). */
+int oracle_kernel_entries(int32_t formula, double p0, double p1, const int64_t *i,
+                          const int64_t *j, int64_t npairs, double *out)
+{
+    if (formula < ORACLE_K_CONSTANT || formula > ORACLE_K_FREE_MOLECULAR) return OR_EINVAL;
+    const kspec K = {1, 0, NULL, NULL, formula, p0, p1};
+    for (int64_t q = 0; q < npairs; ++q) {
+        if (i[q] < 1 || j[q] < 1) return OR_EINVAL;
+        out[q] = kern(&K, i[q], j[q]);
+    }
     return OR_OK;
 }
 
@@ -186,10 +269,11 @@ int oracle_rhs_entries(int64_t M, int32_t R, const double *U, const double *V,
         if (idx[q] < 0 || idx[q] >= M) return OR_EINVAL;
         if (idx[q] == 0) need_pairs = 1;
     }
-    double pairs = need_pairs ? shatter_double_sum(M, R, U, V, n) : 0.0;
+    const kspec K = factors(M, R, U, V);
+    double pairs = need_pairs ? shatter_double_sum(&K, n) : 0.0;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t q = 0; q < nidx; ++q)
-        out[q] = rhs_one(M, R, U, V, lam, n, idx[q] + 1, pairs);
+        out[q] = rhs_one(&K, lam, n, idx[q] + 1, pairs);
     return OR_OK;
 }
 
@@ -756,15 +840,21 @@ void oracle_moments(int64_t M, const double *n, double *mom)
  * log h / 10, log of the last four weighted error norms / 10 (most recent
  * first; entries with no history are 0).  Moments are floored at 1e-300
  * before the log. */
+void oracle_proposer_features(const double *mom, double h,
+                              const double *err_hist, int32_t n_hist, double *x)
+{
+    for (int k = 0; k < 4; ++k) x[k] = log(fmax(mom[k], 1e-300)) / 40.0;
+    x[4] = log(h) / 10.0;
+    for (int q = 0; q < 4; ++q)
+        x[5 + q] = q < n_hist ? log(fmax(err_hist[q], 1e-300)) / 10.0 : 0.0;
+}
+
 void oracle_features(int64_t M, const double *n, double h,
                      const double *err_hist, int32_t n_hist, double *x)
 {
     double mom[4];
     oracle_moments(M, n, mom);
-    for (int k = 0; k < 4; ++k) x[k] = log(fmax(mom[k], 1e-300)) / 40.0;
-    x[4] = log(h) / 10.0;
-    for (int q = 0; q < 4; ++q)
-        x[5 + q] = q < n_hist ? log(fmax(err_hist[q], 1e-300)) / 10.0 : 0.0;
+    oracle_proposer_features(mom, h, err_hist, n_hist, x);
 }
 
 #define NIN 9
@@ -857,3 +947,107 @@ void oracle_adam(double *params, const double *grad, double *m, double *v,
         params[i] -= lr * mh / (sqrt(vh) + eps);
     }
 }
+
+/* ------------------------------------------------------------------ */
+/* Learned step proposer: training rows and decisions.                 */
+/* ------------------------------------------------------------------ */
+
+#define LOG_FACMIN (-1.6094379124341003) /* log 0.2 */
+#define LOG_FACMAX (2.302585092994046)   /* log 10 */
+
+static double clamp_log(double d)
+{
+    return d < LOG_FACMIN ? LOG_FACMIN : (d > LOG_FACMAX ? LOG_FACMAX : d);
+}
+
+/* log of the PI step factor with the default exponents alpha = 0.7/k,
+ * beta = 0.4/k: log clamp(0.9 err^-alpha err_prev^beta, 0.2, 10), and
+ * log 10 for err = 0 (the same rule as the PI controller of
+ * oracle_integrate). */
+static double pi_log(double err, double err_prev, int32_t k)
+{
+    if (err == 0.0) return LOG_FACMAX;
+    const double a = 0.7 / k, b = 0.4 / k;
+    return clamp_log(log(0.9) - a * log(err) + b * log(err_prev));
+}
+
+/* Training rows from a run log (rows x 9: t, h, err, accepted, t_after,
+ * M0..M3 of the state after the attempt).  The network decides the step
+ * after an accepted attempt j that did not follow a rejection; a row is
+ * made for every such j that has a successor attempt j+1 with h_{j+1} > 0
+ * and a finite err_{j+1} > 0.
+ *   features: oracle_proposer_features(moments of row j, h_j,
+ *             err_j, err_{j-1}, err_{j-2}, err_{j-3} as far as they exist)
+ *   target:   the hindsight log step that would have met err_target on the
+ *             next attempt if err scaled as h^k,
+ *             d = clamp(log(h_{j+1}/h_j) + log(err_target/err_{j+1}) / k),
+ *             less the PI rule's log factor at decision j (err_j and
+ *             err_prev = the err of the last accepted attempt before j,
+ *             floored at 1e-4, or 1 when there is none), so that the
+ *             network learns a correction to the PI step.
+ * X (capacity rows x 9) and target (capacity rows) receive the rows in log
+ * order; returns their number. */
+int64_t oracle_proposer_dataset(const double *log_rows, int64_t rows, int32_t k,
+                                double err_target, double *X, double *target)
+{
+    int64_t n = 0;
+    double err_prev = 1.0; /* last accepted err before the current row */
+    for (int64_t j = 0; j + 1 < rows; ++j) {
+        const double *r = log_rows + j * 9, *nx = r + 9;
+        const int accepted = r[3] == 1.0;
+        const int after_reject = j > 0 && log_rows[(j - 1) * 9 + 3] != 1.0;
+        if (accepted && !after_reject && r[1] > 0.0 && nx[1] > 0.0 && nx[2] > 0.0 &&
+            isfinite(nx[2])) {
+            double hist[4];
+            int32_t nh = 0;
+            for (int64_t q = j; q >= 0 && nh < 4; --q) hist[nh++] = log_rows[q * 9 + 2];
+            oracle_proposer_features(r + 5, r[1], hist, nh, X + n * 9);
+            const double d = clamp_log(log(nx[1] / r[1]) + log(err_target / nx[2]) / k);
+            target[n] = d - pi_log(r[2], err_prev, k);
+            ++n;
+        }
+        if (accepted) err_prev = fmax(r[2], 1e-4);
+    }
+    return n;
+}
+
+/* The learned controller's step factor h_next / h at a decision after an
+ * accepted attempt that did not follow a rejection: the network output y
+ * for the features (moments of the new state, h, error history) corrects
+ * the PI rule in log space, h_next / h = exp(clamp(log PI + y)) with PI at
+ * (err = err_hist[0], err_prev) and exponents 0.7/k, 0.4/k. */
+double oracle_learned_factor(const double *params, const double *mom, double h,
+                             const double *err_hist, int32_t n_hist, double err_prev,
+                             int32_t k)
+{
+    double x[NIN], h1[NH], h2[NH], y;
+    oracle_proposer_features(mom, h, err_hist, n_hist, x);
+    mlp_one(params, x, h1, h2, &y);
+    return exp(clamp_log(pi_log(err_hist[0], err_prev, k) + y));
+}
+
+/* Replay of a learned-controller run log (rows x 9 as above): ratio[j] =
+ * h_{j+1} / h_j that the learned controller takes at decision j, for every
+ * accepted attempt j that did not follow a rejection (err_prev: the err of
+ * the last accepted attempt before j, floored at 1e-4, or 1); NaN where
+ * the PI rule decides (after a rejection) or attempt j was rejected.  The
+ * last row's ratio is NaN (no successor). */
+void oracle_learned_steps(const double *params, const double *log_rows, int64_t rows,
+                          int32_t k, double *ratio)
+{
+    double err_prev = 1.0;
+    for (int64_t j = 0; j < rows; ++j) {
+        const double *r = log_rows + j * 9;
+        const int accepted = r[3] == 1.0;
+        const int after_reject = j > 0 && log_rows[(j - 1) * 9 + 3] != 1.0;
+        ratio[j] = NAN;
+        if (accepted && !after_reject && j + 1 < rows) {
+            double hist[4];
+            int32_t nh = 0;
+            for (int64_t q = j; q >= 0 && nh < 4; --q) hist[nh++] = log_rows[q * 9 + 2];
+            ratio[j] = oracle_learned_factor(params, r + 5, r[1], hist, nh, err_prev, k);
+        }
+        if (accepted) err_prev = fmax(r[2], 1e-4);
+    }
+}
+

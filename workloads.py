@@ -32,7 +32,19 @@ class SplitMix64:
         return (self.next_u64() >> 11) * (1.0 / 9007199254740992.0)
 
     def uniforms(self, n):
-        return np.array([self.uniform() for _ in range(n)])
+        """The next n uniforms (the same numbers as n calls of uniform()):
+        the k-th state is seed + k * 0x9E3779B97F4A7C15 mod 2^64, so the
+        whole run is mixed at once in wrapping uint64 arithmetic."""
+        if n <= 0:
+            return np.zeros(0)
+        k = np.arange(1, n + 1, dtype=np.uint64)
+        with np.errstate(over="ignore"):
+            z = np.uint64(self.state) + k * np.uint64(0x9E3779B97F4A7C15)
+            z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+            z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+            z = z ^ (z >> np.uint64(31))
+        self.state = (self.state + n * 0x9E3779B97F4A7C15) & MASK64
+        return (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
 
 
 def sizes(M):
