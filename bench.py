@@ -88,29 +88,93 @@ def step_bytes(M, R, L):
 STEP_LAUNCHES = {"int_a": 1, "int_b": 6, "int_c_fused": 5, "int_c_last": 1}
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
 def cpu_baseline(U, V, lam, n0, per_step_rhs):
     """The FP64 oracle (plain O(M^2) direct sums) timed on the host: one full
-    right-hand side at the start state, converted to DP5 steps/s."""
+    right-hand side at the start state on all host threads (up to 16) and
+    one on a single thread, converted to DP5 steps/s."""
     import oracle
     threads = min(16, os.cpu_count() or 1)
     oracle.lib()
     t0 = time.perf_counter()
     oracle.rhs(U, V, lam, n0, threads=threads)
     dt = time.perf_counter() - t0
-    model = "unknown CPU"
-    try:
-        with open("/proc/cpuinfo") as f:
-            for ln in f:
-                if ln.startswith("model name"):
-                    model = ln.split(":", 1)[1].strip()
-                    break
-    except OSError:
-        pass
+    t0 = time.perf_counter()
+    oracle.rhs(U, V, lam, n0, threads=1)
+    dt1 = time.perf_counter() - t0
+    model = cpu_model()
     return {"value": 1.0 / (per_step_rhs * dt), "unit": "accepted steps/s", "cores": threads,
             "kind": "oracle",
             "sample": f"one direct O(M^2 R) right-hand side at M={n0.size} "
                       f"({dt:.2f} s on {threads} threads of {os.cpu_count()} x {model}), "
-                      f"times {per_step_rhs} per DP5 step"}
+                      f"times {per_step_rhs} per DP5 step",
+            "rhs_evals_per_s": 1.0 / dt,
+            "single_thread": {"value": 1.0 / (per_step_rhs * dt1), "rhs_evals_per_s": 1.0 / dt1,
+                              "cores": 1, "rhs_s": dt1}}
+
+
+def plain_small(smol, W, torch, dev):
+    """The plain-small workload (M = 512, rank-3 kernel a = 1/3, lam = 0.01,
+    monodisperse start, BS3 with PI, rtol 1e-6, atol 1e-12, t_end = 50): one
+    GPU run and the oracle's whole trajectory on the host (all threads up to
+    16, then one thread), with their end-state difference."""
+    import oracle
+    c = W.WORKLOADS["plain-small"]
+    U, V, lam, n0 = W.workload_instance("plain-small")
+    Ud, Vd, nd = (torch.from_numpy(x).to(dev) for x in (U, V, n0))
+    args = (lam, nd, c["t_end"], c["rtol"], c["atol"])
+    smol.integrate(Ud, Vd, *args, method="bs3", raise_on_error=True)  # plan and graph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out, st = smol.integrate(Ud, Vd, *args, method="bs3", raise_on_error=True)
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - t0
+    threads = min(16, os.cpu_count() or 1)
+    res = {"gpu": {"time_to_t_end_s": tg, "accepted_steps_per_s": st["n_accept"] / tg,
+                   "rhs_evals_per_s": st["n_rhs"] / tg, "n_accept": st["n_accept"],
+                   "n_rhs": st["n_rhs"]}}
+    for name, th in (("oracle", threads), ("oracle_single_thread", 1)):
+        t0 = time.perf_counter()
+        ref, rst, _ = oracle.integrate(U, V, lam, n0, c["t_end"], c["rtol"], c["atol"],
+                                       method=oracle.BS32, threads=th)
+        dt = time.perf_counter() - t0
+        res[name] = {"time_to_t_end_s": dt, "cores": th, "accepted_steps_per_s": rst["n_accept"] / dt,
+                     "rhs_evals_per_s": rst["n_rhs"] / dt, "n_accept": rst["n_accept"],
+                     "n_rhs": rst["n_rhs"]}
+    o = out.cpu().numpy()
+    res["rel_diff_gpu_vs_oracle"] = float(abs(o - ref).max() / abs(ref).max())
+    return res
+
+
+def copy_ceiling(torch, dev, nbytes, iters=200):
+    """Mean time of one device-to-device copy of nbytes (nbytes / 2 read and
+    nbytes / 2 written: the same footprint as a kernel that moves nbytes),
+    one launch each, timed with events on torch's current stream."""
+    n = max(1, nbytes // 16)
+    src = torch.ones(n, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(10):
+        dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(iters):
+        dst.copy_(src)
+    b.record()
+    b.synchronize()
+    ms = a.elapsed_time(b) / iters
+    moved = 16 * n
+    return {"bytes": moved, "ms": ms, "GB/s": moved / (ms * 1e-3) / 1e9,
+            "frac": moved / (ms * 1e-3) / HBM_PEAK}
 
 
 def main():
@@ -120,18 +184,21 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--t-end", type=float, default=None, help="shorter runs (profiling)")
-    ap.add_argument("--workload", choices=["single", "batch", "learned", "kernels"],
+    ap.add_argument("--workload", choices=["single", "batch", "learned", "kernels", "precision"],
                     default="single",
                     help="single: the M=65536 DP5 instance (default); batch: the 256-instance "
                          "sweep; learned: train the step proposer, then learned vs PI at "
                          "M=262144; kernels: --steps launches of each RHS kernel plus a 64 MiB "
-                         "device copy (for hardware-counter runs)")
+                         "device copy (for hardware-counter runs); precision: the float-float "
+                         "convolutions against the oracle's trajectory windows and FP64 to t=1e3")
     ap.add_argument("--no-accuracy-check", action="store_true",
                     help="skip the tight reference run that selects rtol (profiling)")
-    ap.add_argument("--train-instances", type=int, default=128)
+    ap.add_argument("--train-instances", type=int, default=512)
+    ap.add_argument("--train-t-end", type=float, default=1e3)
     ap.add_argument("--epochs", type=int, default=100)
-    ap.add_argument("--err-target", type=float, default=0.8,
-                    help="learned workload: error norm the hindsight training targets aim at")
+    ap.add_argument("--err-target", type=float, default=None,
+                    help="learned workload: error norm the hindsight training targets aim at "
+                         "(default: the median accepted norm of the PI training runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); multi-GPU "
@@ -151,6 +218,8 @@ def main():
         return bench_learned(args, smol, W, torch, dev)
     if args.workload == "kernels":
         return bench_kernels(args, smol, W, torch, dev)
+    if args.workload == "precision":
+        return bench_precision(args, smol, W, torch, dev)
     c = W.WORKLOADS["single-large"]
     t_end = args.t_end if args.t_end else c["t_end"]
     U, V, lam, n0 = W.workload_instance("single-large")
@@ -237,9 +306,35 @@ def main():
         "rhs_evals_per_s": n_rhs / elapsed,
         "roofline": roof,
     }
+    roof["copy_same_footprint"] = copy_ceiling(torch, dev, nbytes[dom])
+    roof["copy_rhs_footprint"] = copy_ceiling(torch, dev, rb["rhs"])
+    # the kernel's rate against a plain copy that moves the same bytes in one launch
+    roof["frac_of_copy"] = roof["frac"] / roof["copy_same_footprint"]["frac"]
+    line["rhs_precision"] = rhs_precision_times(smol, torch, Ud, Vd, lam, out.clone())
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(U, V, lam, n0, 6)
+        line["plain_small"] = plain_small(smol, W, torch, dev)
     print(json.dumps(line), flush=True)
+
+
+def rhs_precision_times(smol, torch, U, V, lam, n, iters=200):
+    """Mean time of one whole right-hand side (three kernels, launched by
+    smol_rhs on torch's current stream, timed with events there) in FP64 and
+    in float-float, at the same state."""
+    res = {}
+    for prec in ("fp64", "fp32x2"):
+        out = torch.empty_like(n)
+        for _ in range(5):
+            smol.rhs(U, V, lam, n, out=out, precision=prec)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(iters):
+            smol.rhs(U, V, lam, n, out=out, precision=prec)
+        b.record()
+        b.synchronize()
+        res[prec] = {"ms_per_rhs": a.elapsed_time(b) / iters}
+    res["fp32x2_over_fp64"] = res["fp32x2"]["ms_per_rhs"] / res["fp64"]["ms_per_rhs"]
+    return res
 
 
 def bench_batch(args, smol, W, torch, dev):
@@ -266,6 +361,7 @@ def bench_batch(args, smol, W, torch, dev):
     torch.cuda.synchronize()
     elapsed = (time.perf_counter() - t0) / args.steps
     n_acc = sum(s["n_accept"] for s in stats)
+    n_rhs = sum(s["n_rhs"] for s in stats)
     t0 = time.perf_counter()
     sample = list(range(0, len(insts), 16))
     for i in sample:
@@ -288,6 +384,7 @@ def bench_batch(args, smol, W, torch, dev):
         "single_instance_runs_extrapolated_s": single,
         "speedup_vs_single_runs": single / elapsed,
         "accepted_steps_total": n_acc,
+        "rhs_evals_per_s": n_rhs / elapsed,
         "max_accepted_steps_one_instance": max(s["n_accept"] for s in stats),
         "all_ok": all(s["status"] == 0 for s in stats),
     }
@@ -307,6 +404,11 @@ def bench_kernels(args, smol, W, torch, dev):
     Ud, Vd, nd = (torch.from_numpy(x).to(dev) for x in (U, V, W.exponential_start(M, 300.0)))
     prof = smol.profile_rhs(Ud, Vd, lam, nd, iters=args.steps)
     prof_step = smol.profile_step(Ud, Vd, lam, nd, method="dp5", iters=args.steps)
+    # the same right-hand side in float-float (the k_phase* kernels over cff)
+    ff = rhs_precision_times(smol, torch, Ud, Vd, lam, nd, iters=args.steps)
+    ceil = {k: copy_ceiling(torch, dev, b, iters=args.steps)
+            for k, b in (("int_c_fused", step_bytes(M, R, L)["int_c_fused"]),
+                         ("rhs", rhs_bytes(M, R, L)["rhs"]))}
     nbytes = 64 << 20
     src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
     dst = torch.empty_like(src)
@@ -317,26 +419,91 @@ def bench_kernels(args, smol, W, torch, dev):
     print(json.dumps({"workload": "kernels", "M": M, "R": R, "fft_length": L,
                       "launches": args.steps, "ms_per_launch": dict(prof, **prof_step),
                       "alg_bytes": dict(rhs_bytes(M, R, L), **step_bytes(M, R, L)),
+                      "rhs_evals_per_s": 1e3 / prof["rhs"],
+                      "rhs_precision": ff,
+                      "copy_same_footprint": ceil,
                       "copy_bytes_each_way": nbytes}),
           flush=True)
+
+
+def bench_precision(args, smol, W, torch, dev):
+    """The precision workload: the single-large instance (rank 3, a = 0.45,
+    lam = 0.005) and the rank-4 product kernel (a = 0.3, lam = 0.02), both at
+    M = 65536 from the monodisperse start with DP5(4), rtol 1e-6, atol 1e-12.
+    (1) The first 16 attempts in FP64 and in float-float against the oracle's
+    FP64 windows stored under tests/golden (written by
+    tests/golden/make_oracle_windows.py from the oracle alone); (2) whole runs
+    to t = 1e3 in both precisions, timed, with their max-norm relative
+    difference (the oracle's whole trajectory, about 10^4 direct
+    right-hand sides, is out of reach of a host)."""
+    import numpy as np
+    golden = os.path.join(ROOT, "tests", "golden")
+    c = W.WORKLOADS["single-large"]
+    p = W.WORKLOADS["precision"]
+    cases = {"rank3": (W.brownian_rank3(c["M"], c["a"]), c["lam"], c["t_end"],
+                       "single_large_dp5_w16.npz"),
+             "rank4": (W.product_rank4(p["M"], p["a"]), p["lam"], p["t_eval"],
+                       "precision_rank4_dp5_w16.npz")}
+    res = {}
+    for name, ((U, V), lam, t_w, fixture) in cases.items():
+        Ud, Vd = torch.from_numpy(U).to(dev), torch.from_numpy(V).to(dev)
+        n0 = torch.from_numpy(W.monodisperse(U.shape[1])).to(dev)
+        ref = np.load(os.path.join(golden, fixture))
+        r = {}
+        for prec in ("fp64", "fp32x2"):
+            out, st = smol.integrate(Ud, Vd, lam, n0, t_w, 1e-6, 1e-12, method="dp5",
+                                     precision=prec, max_steps=16)
+            r["window_rel_err_vs_oracle_" + prec] = float(
+                np.abs(out.cpu().numpy() - ref["n"]).max() / np.abs(ref["n"]).max())
+        outs = {}
+        for prec in ("fp64", "fp32x2"):
+            smol.integrate(Ud, Vd, lam, n0, 1.0, 1e-6, 1e-12, method="dp5", precision=prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out, st = smol.integrate(Ud, Vd, lam, n0, p["t_eval"], 1e-6, 1e-12, method="dp5",
+                                     precision=prec, raise_on_error=True)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            outs[prec] = out
+            r[prec] = {"time_to_t_s": dt, "n_accept": st["n_accept"], "n_reject": st["n_reject"],
+                       "rhs_evals_per_s": st["n_rhs"] / dt}
+        r["rel_diff_fp32x2_vs_fp64_at_t"] = ((outs["fp32x2"] - outs["fp64"]).abs().max()
+                                            / outs["fp64"].abs().max()).item()
+        res[name] = r
+        print(f"bench: precision {name}: {r}", file=sys.stderr, flush=True)
+    line = {"metric": "float-float convolutions: max relative error vs the FP64 oracle "
+                      "(16-attempt windows) and vs FP64 at t=1e3",
+            "value": max(res[k]["rel_diff_fp32x2_vs_fp64_at_t"] for k in res),
+            "unit": "relative error", "n_gpus": 1, "steps": 1, "warmup": 1,
+            "ms_per_step": 1e3 * res["rank3"]["fp32x2"]["time_to_t_s"],
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64 state, fp32x2 convolutions", "data": "synthetic",
+            "config": {"workload": "precision: M=65536 rank-3 a=0.45 lam=0.005 and rank-4 "
+                                   "a=0.3 lam=0.02, monodisperse, DP5(4), rtol=1e-6, "
+                                   "atol=1e-12, t=1e3", "parallelism": "1 GPU"},
+            "cases": res}
+    print(json.dumps(line), flush=True)
 
 
 def bench_learned(args, smol, W, torch, dev):
     """Learned step proposer against PI on the large instance (M = 262144,
     a = 0.4, lam = 0.01, monodisperse start, DP5(4), rtol 1e-6, t_end 1e4).
 
-    Training data: per-attempt logs of PI runs (DP5, rtol 1e-6, t_end 1e4) on
-    instances drawn from the batched sweep's distribution (seed 1), run as one
-    batch; hindsight targets for err = 0.8; weighted-MSE training with Adam
-    (lr 1e-3, overshoot weight 4) from seed-12345 initial weights, all in the
-    library's kernels.  Then one run with each controller, timed, and both
-    compared with a tight run (rtol 1e-10, atol 1e-16)."""
+    Training data: per-attempt logs of PI runs (DP5, rtol 1e-6, to the batched
+    sweep's t_end = 1e3) on 512 instances drawn from the batched sweep's
+    distribution (seed 1), run in batches of 128; hindsight targets for the error norm the PI runs accept
+    at (their median accepted norm, unless --err-target is given);
+    weighted-MSE training with Adam (lr 1e-3, overshoot weight 4) from
+    seed-12345 initial weights, all in the library's kernels.  Then one run
+    with each controller, timed, and both compared with a tight run
+    (rtol 1e-10, atol 1e-16)."""
     import numpy as np
     c = W.WORKLOADS["learned-proposer"]
     t_end = args.t_end if args.t_end else c["t_end"]
+    t_train_end = args.train_t_end
     cap = 40000
     draws = W.batch_draws(args.train_instances, seed=1)
-    Xs, Ts = [], []
+    logs_all = []
     t_runs = 0.0
     for lo in range(0, len(draws), 128):
         insts, logs = [], []
@@ -344,7 +511,7 @@ def bench_learned(args, smol, W, torch, dev):
             U, V, lam, n0 = W.batch_instance(d)
             log = torch.zeros((cap, 9), dtype=torch.float64, device=dev)
             insts.append(dict(U=torch.from_numpy(U).to(dev), V=torch.from_numpy(V).to(dev),
-                              lam=lam, n0=torch.from_numpy(n0).to(dev), t_end=t_end,
+                              lam=lam, n0=torch.from_numpy(n0).to(dev), t_end=t_train_end,
                               rtol=c["rtol"], atol=c["atol"], log=log))
             logs.append(log)
         torch.cuda.synchronize()
@@ -353,13 +520,20 @@ def bench_learned(args, smol, W, torch, dev):
         torch.cuda.synchronize()
         t_runs += time.perf_counter() - t0
         for log, st in zip(logs, stats):
-            X, tg = smol.proposer_dataset(log, min(cap, st["n_accept"] + st["n_reject"]), "dp5",
-                                          args.err_target)
-            Xs.append(X)
-            Ts.append(tg)
+            logs_all.append((log, min(cap, st["n_accept"] + st["n_reject"])))
         print(f"bench: training runs {lo + len(insts)}/{len(draws)} ({t_runs:.1f} s)",
               file=sys.stderr, flush=True)
-        del insts, logs
+        del insts
+    err_target = args.err_target
+    if err_target is None:
+        acc = torch.cat([lg[:n][lg[:n, 3] == 1.0, 2] for lg, n in logs_all])
+        err_target = float(acc.median().item())
+    Xs, Ts = [], []
+    for log, n in logs_all:
+        X, tg = smol.proposer_dataset(log, n, "dp5", err_target)
+        Xs.append(X)
+        Ts.append(tg)
+    del logs_all
     X = torch.cat(Xs).contiguous()
     tg = torch.cat(Ts).contiguous()
     params = torch.from_numpy(W.mlp_init(12345).astype(np.float32)).to(dev)
@@ -387,6 +561,7 @@ def bench_learned(args, smol, W, torch, dev):
         dt = time.perf_counter() - t0
         err = ((out - ref).abs().max() / ref.abs().max()).item()
         res[ctrl] = {"time_to_t_end_s": dt, "n_accept": st["n_accept"],
+                     "rhs_evals_per_s": st["n_rhs"] / dt,
                      "n_reject": st["n_reject"], "n_rhs": st["n_rhs"],
                      "reject_rate": st["n_reject"] / max(1, st["n_accept"] + st["n_reject"]),
                      "n_fallback": st["n_fallback"], "rel_err_vs_tight_run": err}
@@ -402,12 +577,13 @@ def bench_learned(args, smol, W, torch, dev):
         "dtype": "f64 (network f32)", "data": "synthetic",
         "config": {"workload": f"learned-proposer: M=262144, R=3, a=0.4, lam=0.01, monodisperse, "
                                f"DP5(4), rtol=1e-6, atol=1e-12, t_end={t_end:g}; trained on "
-                               f"{len(draws)} sweep-distributed runs, error target "
-                               f"{args.err_target:g}", "parallelism": "1 GPU"},
+                               f"{len(draws)} sweep-distributed runs to t={t_train_end:g}, "
+                               f"error target {err_target:.3g}", "parallelism": "1 GPU"},
         "learned": res["learned"], "pi": res["pi"],
         "speedup_vs_pi": res["pi"]["time_to_t_end_s"] / res["learned"]["time_to_t_end_s"],
         "rhs_ratio_vs_pi": res["learned"]["n_rhs"] / res["pi"]["n_rhs"],
         "training": {"runs_s": t_runs, "rows": int(X.shape[0]), "epochs": args.epochs,
+                     "err_target": err_target, "instances": len(draws), "t_end": t_train_end,
                      "train_s": t_train, "loss_first": loss[0].item(),
                      "loss_last": loss[-1].item()},
         "batched_sweep": sweep,

@@ -17,7 +17,12 @@
  *   - `stream` is a hipStream_t; NULL means the null stream.
  *   - Every call returns an int status (SMOL_OK or a negative code) and
  *     never throws across the ABI.  smol_strerror() names a code.
- *   - Calls are not re-entrant for the same plan from several host threads.
+ *   - Calls that share a plan (same device, M, R, precision) reuse its
+ *     workspaces.  The library orders them: work a call enqueues on one
+ *     stream waits (hipStreamWaitEvent) for the plan's previous work on
+ *     another stream.  Under HIP graph capture that ordering is not added;
+ *     the capturing caller orders captured calls that share a plan.  Host
+ *     threads are serialised by a library lock.
  */
 #ifndef SMOL_H
 #define SMOL_H
@@ -99,7 +104,7 @@ typedef struct {
  * with FFTs of length L = nextpow2(2M-2), the death and shattering sums are
  * 4R reductions.
  *
- * M >= 1; 1 <= R <= 16; lam >= 0 and finite; n, dndt: M doubles each, on
+ * M >= 1; 1 <= R <= 32; lam >= 0 and finite; n, dndt: M doubles each, on
  * the device; dndt must not alias n.  precision: SMOL_FP64 or SMOL_FP32X2
  * (the convolutions in float-float arithmetic, everything else FP64).
  * Asynchronous on `stream`.  Errors: SMOL_EINVAL, SMOL_ENOMEM,
@@ -136,6 +141,37 @@ int smol_rhs_noalloc(int64_t M, int32_t R, const double *U, const double *V,
                      double lambda, const double *n, double *dndt,
                      void *stream);
 
+/* Kernels given by a formula (Sec. 3.1), for smol_lowrank. */
+enum {
+    SMOL_KERNEL_CONSTANT = 1,      /* K_ij = p0 */
+    SMOL_KERNEL_BROWNIAN = 2,      /* K_ij = (i/j)^p0 + (j/i)^p0 + p1 */
+    SMOL_KERNEL_FREE_MOLECULAR = 3 /* K_ij = (i^(1/3) + j^(1/3))^2 sqrt(1/i + 1/j) */
+};
+
+/* smol_lowrank -- low-rank factors K ~= U V (K_ij ~= sum_a U[a*M + i-1]
+ * V[a*M + j-1]) of a kernel given by a formula, for kernels with no exact
+ * low-rank form such as the free-molecular kernel of Sec. 3.1, so that the
+ * O(M R log M) right-hand side and the integrators apply to them.  Adaptive
+ * cross approximation with partial pivoting (Bebendorf 2000), on the GPU:
+ * each term is one residual row and one residual column of K, evaluated on
+ * demand; the rank grows until a new term's Frobenius norm is at most tol
+ * times that of the approximation (that term is not kept), or reaches
+ * max_rank.  The error
+ * |K - U V| is not bounded entrywise by tol (it is measured in the tests).
+ *
+ * M >= 1; kernel: SMOL_KERNEL_*; p0, p1 its parameters (finite);
+ * tol >= 0; 1 <= max_rank <= 32.  U, V: device arrays of max_rank * M
+ * doubles each (alpha-major, the layout smol_rhs takes), distinct; rows
+ * beyond *rank are left unspecified.  rank (HOST): the rank built; est
+ * (HOST, may be NULL): the relative Frobenius norm of the last term
+ * computed (the one that stopped the growth, or the last kept one when
+ * max_rank or M ended it).
+ * Synchronous.  Errors: SMOL_EINVAL, SMOL_ENOMEM, SMOL_EDEVICE,
+ * SMOL_EUNSUPPORTED (M beyond the right-hand side's limit). */
+int smol_lowrank(int64_t M, int32_t kernel, double p0, double p1, double tol,
+                 int32_t max_rank, double *U, double *V, int32_t *rank,
+                 double *est, void *stream);
+
 /*
  * smol_integrate -- integrate dn/dt = S(n), n(0) = n0 (Sec. 2, Eq. (5)) to
  * t_end with an embedded explicit Runge--Kutta pair and adaptive steps
@@ -161,6 +197,29 @@ int smol_integrate(int64_t M, int32_t R, const double *U, const double *V,
                    double atol, int32_t method, int32_t precision,
                    double *n_out, smol_stats *stats, void *stream);
 
+/* Checkpoint of a run (smol_options.state): what a run needs to continue
+ * exactly as if it had not stopped -- the time, the next step, the
+ * controller's memory, the counters and S at the state (the first stage of
+ * the next attempt, first-same-as-last).  The state vector itself is the
+ * run's n_out, passed back as n0 when resuming. */
+typedef struct {
+    double t;            /* time of the state */
+    double h;            /* next step to attempt (before clipping to t_end) */
+    double err;          /* norm of the last attempt */
+    double err_prev;     /* PI memory: last accepted norm, floored at 1e-4 */
+    double err_hist[4];  /* norms of the last four attempts, most recent
+                            first (learned controller features) */
+    int64_t n_rhs, n_accept, n_reject;  /* counters, carried on */
+    int32_t n_hist;      /* entries of err_hist in use */
+    int32_t rejected;    /* the last attempt was rejected */
+    int32_t valid;       /* in: 1 = resume from this state, 0 = start at
+                            t = 0; out: 1 when a resumable state was written
+                            (status SMOL_OK or SMOL_EMAXSTEPS), else 0 */
+    int32_t n_fallback;  /* learned controller: PI fallbacks so far */
+    double *k1;          /* device, M doubles (natural layout): S(n) at
+                            the state; required whenever `state` is set */
+} smol_state;
+
 /* Options of smol_integrate_ex; zero-initialise and set what you need. */
 typedef struct {
     double h0;          /* > 0: first step; 0: starting procedure */
@@ -179,10 +238,23 @@ typedef struct {
     const double *source; /* constant sources P_s of Eq. (3): M doubles on
                            the device, or NULL (the right-hand side is then
                            S(n) + source throughout the run) */
+    smol_state *state;  /* HOST pointer or NULL: checkpoint in and out.
+                           With state->valid == 1 the run resumes from it:
+                           n0 is the state at time state->t (the n_out of
+                           the run that wrote it), no starting-step
+                           procedure runs, and the counters continue;
+                           max_steps and the log count this call's attempts
+                           only.  Resuming with the same scheme, controller,
+                           tolerances, options and t_end continues the run
+                           bitwise as if it had not stopped.  On return the
+                           run's final checkpoint is written to *state
+                           (k1 receives S at n_out). */
 } smol_options;
 
 /* smol_integrate with options.  The number of log rows written is
- * min(log_cap, n_accept + n_reject). */
+ * min(log_cap, attempts of this call).  EINVAL also for a state without k1,
+ * or a resumed state with a non-finite or negative t, or h <= 0; a resumed
+ * state at t >= t_end returns n0 after 0 attempts. */
 int smol_integrate_ex(int64_t M, int32_t R, const double *U, const double *V,
                       double lambda, const double *n0, double t_end,
                       double rtol, double atol, int32_t method,
@@ -208,15 +280,22 @@ typedef struct {
 /*
  * smol_integrate_batch -- advance n_inst independent instances (uneven M,
  * kernels, lambda, tolerances) with per-instance step sizes and
- * accept/reject, in one persistent launch.  `inst` and `stats` are HOST
- * arrays of n_inst entries.  A failing instance records its status in its
- * own stats entry and does not stop the others; the call returns SMOL_OK
- * when every instance is launched and finishes (check each stats[i].status).
- * Options apply to every instance (opts->log must be NULL: logs are per
- * instance).  Each phase of a step attempt is one launch over all running
- * instances (a block-to-instance table), replayed as a hipGraph; the
- * tables shrink as instances finish.  Every instance reproduces its
- * single-instance smol_integrate_ex result bitwise.
+ * accept/reject.  `inst` and `stats` are HOST arrays of n_inst entries.  A
+ * failing instance records its status in its own stats entry and does not
+ * stop the others; the call returns SMOL_OK when every instance is launched
+ * and finishes (check each stats[i].status).  Options apply to every
+ * instance (opts->log must be NULL: logs are per instance; opts->state must
+ * be NULL: batched runs start at t = 0).
+ * Instances are grouped by transform length.  For each group, every kernel
+ * of a step attempt is one launch over that group's running instances (a
+ * block-to-instance table) under the group's launch schedule; each group's
+ * chain of step attempts is captured as its own hipGraph and replayed on
+ * one of four library streams (default priority), so the groups run side by
+ * side; the starting steps run on `stream`, which is synchronised before
+ * the replays, and the call returns after all of them.  When the number of
+ * running instances halves, the tables are rebuilt over the live ones and
+ * the graphs captured again.  Every instance runs exactly the kernels of its
+ * single-instance run and reproduces its smol_integrate_ex result bitwise.
  */
 int smol_integrate_batch(int32_t n_inst, const smol_instance *inst,
                          int32_t method, int32_t precision,
@@ -229,7 +308,8 @@ int smol_integrate_batch(int32_t n_inst, const smol_instance *inst,
  * accepted attempt: log M0..log M3 of the new state divided by 40, log h
  * divided by 10, log err of the last four attempts (most recent first,
  * missing ones 0) divided by 10.  Output y: a correction to the PI rule,
- * log(h_next / h) = log(PI factor) + y, clamped to [log 0.2, log 10]; right
+ * log(h_next / h) = log(PI factor) + y, clamped to [log 0.2, log 10], and
+ * not above log(PI factor) when the attempt's err exceeds 0.5; right
  * after a rejection, or for non-finite features or output, the PI rule alone
  * is used (counted in smol_stats.n_fallback).  The embedded error estimate
  * still accepts or rejects every step. */

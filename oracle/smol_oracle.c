@@ -120,14 +120,8 @@ static kspec factors(int64_t M, int32_t R, const double *U, const double *V)
     return k;
 }
 
-static double kern(const kspec *K, int64_t i, int64_t j)
+static __attribute__((noinline)) double kern_formula(const kspec *K, int64_t i, int64_t j)
 {
-    if (K->R > 0) {
-        double k = 0.0;
-        for (int32_t a = 0; a < K->R; ++a)
-            k += K->U[(int64_t)a * K->M + (i - 1)] * K->V[(int64_t)a * K->M + (j - 1)];
-        return k;
-    }
     const double x = (double)i, y = (double)j;
     switch (K->formula) {
     case ORACLE_K_CONSTANT: return K->p0;
@@ -137,6 +131,17 @@ static double kern(const kspec *K, int64_t i, int64_t j)
         return c * c * sqrt(1.0 / x + 1.0 / y);
     }
     }
+}
+
+static inline __attribute__((always_inline)) double kern(const kspec *K, int64_t i, int64_t j)
+{
+    if (K->R > 0) {
+        double k = 0.0;
+        for (int32_t a = 0; a < K->R; ++a)
+            k += K->U[(int64_t)a * K->M + (i - 1)] * K->V[(int64_t)a * K->M + (j - 1)];
+        return k;
+    }
+    return kern_formula(K, i, j);
 }
 
 static void set_threads(int32_t nthreads)
@@ -1015,7 +1020,8 @@ int64_t oracle_proposer_dataset(const double *log_rows, int64_t rows, int32_t k,
  * accepted attempt that did not follow a rejection: the network output y
  * for the features (moments of the new state, h, error history) corrects
  * the PI rule in log space, h_next / h = exp(clamp(log PI + y)) with PI at
- * (err = err_hist[0], err_prev) and exponents 0.7/k, 0.4/k. */
+ * (err = err_hist[0], err_prev) and exponents 0.7/k, 0.4/k; when err
+ * exceeds 0.5 the factor is at most PI's. */
 double oracle_learned_factor(const double *params, const double *mom, double h,
                              const double *err_hist, int32_t n_hist, double err_prev,
                              int32_t k)
@@ -1023,7 +1029,10 @@ double oracle_learned_factor(const double *params, const double *mom, double h,
     double x[NIN], h1[NH], h2[NH], y;
     oracle_proposer_features(mom, h, err_hist, n_hist, x);
     mlp_one(params, x, h1, h2, &y);
-    return exp(clamp_log(pi_log(err_hist[0], err_prev, k) + y));
+    const double pi = pi_log(err_hist[0], err_prev, k);
+    double d = clamp_log(pi + y);
+    if (err_hist[0] > 0.5 && d > pi) d = pi;
+    return exp(d);
 }
 
 /* Replay of a learned-controller run log (rows x 9 as above): ratio[j] =

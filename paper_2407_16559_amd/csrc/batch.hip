@@ -1,13 +1,14 @@
 // Batched integration of many independent instances (uneven M, kernels,
 // lambda and tolerances), each with its own step size, accept / reject and
-// status.  Every kernel of a step attempt is ONE launch over all instances:
-// a block-to-instance table gives each workgroup its instance and unit, a
-// switch selects the instance's transform shape, and per-instance control
-// blocks carry the state, so the attempt is captured once as a hipGraph and
-// replayed until every instance is done (finished instances' workgroups
-// return at entry).  With hundreds of instances each launch holds tens of
-// thousands of workgroups, which fills the chip and hides memory latency
-// that a single small instance cannot.
+// status, carried in per-instance control blocks.  Instances are grouped by
+// transform length (shape).  Every kernel of a step attempt is one launch
+// per shape over that shape's instances: block-to-instance tables give each
+// workgroup its instance and unit, and the shape's tuned launch schedule
+// applies.  Each shape's chain of step attempts is captured once as its own
+// hipGraph and replayed on one of four streams, so the shapes run side by
+// side; finished instances' workgroups return at entry, and when the
+// running set halves the tables are rebuilt over the live instances and the
+// graphs captured again.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -152,7 +153,7 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
     if (precision != SMOL_FP64 && precision != SMOL_FP32X2) return SMOL_EINVAL;
     smol_options o{};
     if (opts) o = *opts;
-    if (o.h0 < 0 || o.h_min < 0 || o.max_steps < 0 || o.log) return SMOL_EINVAL;
+    if (o.h0 < 0 || o.h_min < 0 || o.max_steps < 0 || o.log || o.state) return SMOL_EINVAL;
     if (!controller_valid(o.controller)) return SMOL_EINVAL;
     for (int i = 0; i < n_inst; ++i) {
         const smol_instance &q = inst[i];

@@ -5,7 +5,7 @@
 
 #define SMOL_WG 256            // threads per workgroup (4 wave64)
 #define SMOL_WAVES (SMOL_WG / 64)
-#define SMOL_MAX_R 16
+#define SMOL_MAX_R 32
 #define SMOL_LOG_TW 10         // unit-root tables have 2^10 entries
 #define SMOL_TW (1 << SMOL_LOG_TW)
 #define SMOL_LOG_LMAX 20       // longest convolution transform: 2^20

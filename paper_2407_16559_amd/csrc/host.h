@@ -45,6 +45,9 @@ inline int fft_log2(int64_t M)
 // order q of each scheme, indexed by SMOL_BS32 .. SMOL_RK4_DBL.
 static const int k_scheme_stages[5] = {4, 7, 7, 6, 12};
 static const int k_scheme_q[5] = {2, 4, 4, 2, 4};
+// Stage slot that alternates with slot 0 as the first stage (the fsal field
+// of each scheme's tableau in integrate.h).
+static const int k_scheme_fsal[5] = {3, 6, 6, 5, 5};
 
 // SMOL_OK for a known scheme, SMOL_EINVAL otherwise.
 inline int check_method(int32_t method)

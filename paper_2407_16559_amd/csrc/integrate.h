@@ -408,6 +408,7 @@ __device__ inline void block_sum_epart(const double *ep, int njobs, double *tot)
 #define MLP_NPARAM (MLP_OFF_B3 + 1)
 #define MLP_LOG_FMIN (-1.6094379124341003)  // log 0.2
 #define MLP_LOG_FMAX (2.302585092994046)    // log 10
+#define MLP_CAP_ERR 0.5  // above this error norm the learned step never exceeds PI's
 
 // log of the PI factor clamp(0.9 err^-alpha err_prev^beta, 0.2, 10)
 // (err = 0: 10), the base the learned proposer corrects.
@@ -543,6 +544,9 @@ __device__ inline void controller_step(const IntegDev &I, int njobs)
                 learned = true;
                 const double base = pi_log_factor(err, c.err_prev, c.alpha, c.beta);
                 dlog = fmin(fmax(base + (double)y, MLP_LOG_FMIN), MLP_LOG_FMAX);
+                // near the acceptance limit err grows much faster than h^k
+                // (stability), so there the network may only shrink the step
+                if (err > MLP_CAP_ERR && dlog > base) dlog = base;
             }
         }
     }

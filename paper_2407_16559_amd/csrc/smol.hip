@@ -18,8 +18,8 @@ SMOL_HIDDEN std::mutex g_mu;
 #define SMOL_VERSION "0.1.0"
 
 // --------------------------------------------------------------------------
-// Kernels of this unit: layout conversion, starting step, controller.  The
-// right-hand-side phase kernels live in phases_a/b/c.hip (see sched.h).
+// Kernels of this unit: layout conversion, starting step, controller, resume.
+// The right-hand-side phase kernels live in phases_a/b/c.hip (see sched.h).
 // --------------------------------------------------------------------------
 
 // Layout conversion of `rows` vectors of M sizes: natural <-> transposed.
@@ -43,6 +43,19 @@ __global__ void k_from_tr(const double *src, double *dst, int64_t M, int logL)
 __global__ __launch_bounds__(SMOL_WG) void k_init_h0(IntegDev I, int njobs) { init_h0_step(I, njobs); }
 __global__ __launch_bounds__(SMOL_WG) void k_init_h(IntegDev I, int njobs) { init_h_step(I, njobs); }
 __global__ __launch_bounds__(SMOL_WG) void k_ctrl(IntegDev I, int njobs) { controller_step(I, njobs); }
+
+// Resume from a checkpoint: the smallest step at the state's time, then the
+// next attempt prepared as the interrupted run would have prepared it (after
+// a rejection the step is not raised to the minimum).  One thread.
+__global__ void k_resume(IntegDev I)
+{
+    if (threadIdx.x) return;
+    IntegCtl &c = *I.ctl;
+    double ms = 10.0 * fabs(nextafter(c.t, INFINITY) - c.t);
+    if (c.h_min > ms) ms = c.h_min;
+    c.min_step = ms;
+    prepare_attempt(c, !c.rejected);
+}
 
 // --------------------------------------------------------------------------
 // Host side
@@ -70,6 +83,11 @@ struct Plan {
     // launch schedule: variant of kernels A, B, C and their grids
     int var[3] = {0, 0, 0};
     PhaseDims dA{}, dB{}, dC{}, dCf{};
+    // stream order of the workspaces: the last call that enqueued work using
+    // them without waiting for it recorded used_ev on used_s
+    hipEvent_t used_ev = nullptr;
+    hipStream_t used_s = nullptr;
+    bool busy = false;
 };
 
 // Schedule variants per transform length for FP64 plans (float-float plans
@@ -144,6 +162,7 @@ int set_plan_sched(Plan *p, const int *v)
 void free_plan(Plan *p)
 {
     if (!p) return;
+    if (p->used_ev) (void)hipEventDestroy(p->used_ev);
     (void)hipFree(p->Z);  // Qp lives in the same allocation
     (void)hipFree(p->red_part);
     for (auto &g : p->graph)
@@ -204,6 +223,26 @@ int get_plan(int64_t M, int R, int precision, Plan **out)
     *out = p;
     return SMOL_OK;
 }
+
+// A plan's workspaces are reused by every call with its (device, M, R,
+// precision).  Work enqueued on stream s waits for the previous call's work
+// when that call used another stream and may still be running.
+int plan_enter(Plan *p, hipStream_t s)
+{
+    if (p->busy && p->used_s != s) HIP_TRY(hipStreamWaitEvent(s, p->used_ev, 0));
+    return SMOL_OK;
+}
+// After enqueueing work on s that the caller does not wait for.
+int plan_leave_async(Plan *p, hipStream_t s)
+{
+    if (!p->used_ev) HIP_TRY(hipEventCreateWithFlags(&p->used_ev, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(p->used_ev, s));
+    p->used_s = s;
+    p->busy = true;
+    return SMOL_OK;
+}
+// After the call has synchronised s: nothing of the plan's is in flight.
+void plan_leave_sync(Plan *p) { p->busy = false; }
 
 RhsPlanDev dev_plan(const Plan *p, const DevRoots *r, const double *U, const double *V, double lam)
 {
@@ -372,7 +411,14 @@ extern "C" int smol_rhs_ex(int64_t M, int32_t R, const double *U, const double *
     ep.mode = C_RHS;
     ep.y = n;
     ep.out = dndt;
-    return launch_rhs(p, P, in, ep, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    // under graph capture the caller orders the captured work itself
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &cs));
+    const bool track = cs == hipStreamCaptureStatusNone;
+    if (track && (rc = plan_enter(p, s))) return rc;
+    if ((rc = launch_rhs(p, P, in, ep, s))) return rc;
+    return track ? plan_leave_async(p, s) : SMOL_OK;
 }
 
 extern "C" int smol_rhs(int64_t M, int32_t R, const double *U, const double *V, double lambda,
@@ -432,11 +478,27 @@ extern "C" int smol_integrate_ex(int64_t M, int32_t R, const double *U, const do
     if (opts) o = *opts;
     if (o.h0 < 0 || o.h_min < 0 || o.max_steps < 0 || (o.log && o.log_cap < 0)) return SMOL_EINVAL;
     if (!controller_valid(o.controller)) return SMOL_EINVAL;
+    smol_state *cp = o.state;
+    if (cp && !cp->k1) return SMOL_EINVAL;
+    const bool resume = cp && cp->valid;
+    if (resume && (!std::isfinite(cp->t) || cp->t < 0 || !std::isfinite(cp->h) || !(cp->h > 0) ||
+                   cp->n_hist < 0 || cp->n_hist > 4))
+        return SMOL_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     if (stats) memset(stats, 0, sizeof(*stats));
-    if (t_end == 0.0) {
+    if (t_end == 0.0 || (resume && cp->t >= t_end)) {
         if (n_out != n0) HIP_TRY(hipMemcpyAsync(n_out, n0, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));
+        if (resume && stats) {
+            stats->n_rhs = cp->n_rhs;
+            stats->n_accept = cp->n_accept;
+            stats->n_reject = cp->n_reject;
+            stats->t = cp->t;
+            stats->h = cp->h;
+            stats->err = cp->err;
+            stats->n_fallback = cp->n_fallback;
+        }
+        if (cp && !resume) cp->valid = 0;  // no step taken: no checkpoint
         return SMOL_OK;
     }
     std::lock_guard<std::mutex> lk(g_mu);
@@ -445,6 +507,7 @@ extern "C" int smol_integrate_ex(int64_t M, int32_t R, const double *U, const do
     if ((rc = get_plan(M, R, precision, &p))) return rc;
     if ((rc = get_roots(p->dev, &r))) return rc;
     if ((rc = alloc_integ(p))) return rc;
+    if ((rc = plan_enter(p, s))) return rc;
     const IntegDev I = integ_dev(p, r);
     IntegCtl &c = *p->host;
     memset(&c, 0, sizeof(c));
@@ -463,6 +526,19 @@ extern "C" int smol_integrate_ex(int64_t M, int32_t R, const double *U, const do
         c.mlp = proposer_weights(p->dev);
         if (!c.mlp) return SMOL_EINVAL;  // smol_proposer_set first
     }
+    if (resume) {
+        c.t = cp->t;
+        c.h = cp->h;
+        c.err = cp->err;
+        c.err_prev = cp->err_prev;
+        for (int q = 0; q < 4; ++q) c.err_hist[q] = cp->err_hist[q];
+        c.n_hist = cp->n_hist;
+        c.rejected = cp->rejected ? 1 : 0;
+        c.n_rhs = cp->n_rhs;
+        c.n_accept = cp->n_accept;
+        c.n_reject = cp->n_reject;
+        c.n_fallback = cp->n_fallback;
+    }
     HIP_TRY(hipMemcpyAsync(p->ctl, &c, sizeof(c), hipMemcpyHostToDevice, s));
     // the integrator keeps every vector in the transposed layout
     hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, U, I.Ut, M, R, M, I.Mt, p->logL);
@@ -472,12 +548,19 @@ extern "C" int smol_integrate_ex(int64_t M, int32_t R, const double *U, const do
         hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, o.source, I.src, M, 1, M, I.Mt,
                            p->logL);
     const int nC = p->dC.jobs;
-    // starting step: S(n0), h0, S(n0 + h0 f0), h
-    if ((rc = launch_stage(p, I, method, 0, 0, s))) return rc;
-    hipLaunchKernelGGL(k_init_h0, dim3(1), dim3(SMOL_WG), 0, s, I, nC);
-    if (!(o.h0 > 0)) {
-        if ((rc = launch_stage(p, I, method, 1, 0, s))) return rc;
-        hipLaunchKernelGGL(k_init_h, dim3(1), dim3(SMOL_WG), 0, s, I, nC);
+    if (resume) {
+        // the checkpoint's S(n) is the first stage (slot 0 at parity 0)
+        hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, cp->k1, I.kslot[0], M, 1, M, I.Mt,
+                           p->logL);
+        hipLaunchKernelGGL(k_resume, dim3(1), dim3(64), 0, s, I);
+    } else {
+        // starting step: S(n0), h0, S(n0 + h0 f0), h
+        if ((rc = launch_stage(p, I, method, 0, 0, s))) return rc;
+        hipLaunchKernelGGL(k_init_h0, dim3(1), dim3(SMOL_WG), 0, s, I, nC);
+        if (!(o.h0 > 0)) {
+            if ((rc = launch_stage(p, I, method, 1, 0, s))) return rc;
+            hipLaunchKernelGGL(k_init_h, dim3(1), dim3(SMOL_WG), 0, s, I, nC);
+        }
     }
     HIP_TRY(hipGetLastError());
     hipGraphExec_t ge;
@@ -495,11 +578,30 @@ extern "C" int smol_integrate_ex(int64_t M, int32_t R, const double *U, const do
         if (chunk > 64) chunk = 64;
         if (chunk < 1) chunk = 1;
     }
-    hipLaunchKernelGGL(k_from_tr, dim3(256), dim3(256), 0, s, I.nb[c.cur], n_out, M, p->logL);
+    const IntegCtl &cf = c;
+    hipLaunchKernelGGL(k_from_tr, dim3(256), dim3(256), 0, s, I.nb[cf.cur], n_out, M, p->logL);
+    if (cp)  // S at n_out: the first stage of the next attempt
+        hipLaunchKernelGGL(k_from_tr, dim3(256), dim3(256), 0, s,
+                           I.kslot[cf.kp ? k_scheme_fsal[method] : 0], cp->k1, M, p->logL);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
-    stats_from(c, stats);
-    return c.status;
+    plan_leave_sync(p);
+    stats_from(cf, stats);
+    if (cp) {
+        cp->t = cf.t;
+        cp->h = cf.h;
+        cp->err = cf.err;
+        cp->err_prev = cf.err_prev;
+        for (int q = 0; q < 4; ++q) cp->err_hist[q] = cf.err_hist[q];
+        cp->n_hist = cf.n_hist;
+        cp->rejected = cf.rejected;
+        cp->n_rhs = cf.n_rhs;
+        cp->n_accept = cf.n_accept;
+        cp->n_reject = cf.n_reject;
+        cp->n_fallback = cf.n_fallback;
+        cp->valid = (cf.status == SMOL_OK || cf.status == SMOL_EMAXSTEPS) ? 1 : 0;
+    }
+    return cf.status;
 }
 
 extern "C" int smol_integrate(int64_t M, int32_t R, const double *U, const double *V,
@@ -559,6 +661,7 @@ extern "C" int smol_profile_rhs(int64_t M, int32_t R, const double *U, const dou
     if ((rc = get_roots(p->dev, &r))) return rc;
     if ((rc = alloc_integ(p))) return rc;
     hipStream_t s = (hipStream_t)stream;
+    if ((rc = plan_enter(p, s))) return rc;
     const IntegDev I = integ_dev(p, r);
     hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, U, I.Ut, M, R, M, I.Mt, p->logL);
     hipLaunchKernelGGL(k_to_tr, dim3(256), dim3(256), 0, s, V, I.Vt, M, R, M, I.Mt, p->logL);
@@ -576,6 +679,7 @@ extern "C" int smol_profile_rhs(int64_t M, int32_t R, const double *U, const dou
     hipLaunchKernelGGL(k_from_tr, dim3(256), dim3(256), 0, s, I.kslot[0], dndt, M, p->logL);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
+    plan_leave_sync(p);
     return SMOL_OK;
 }
 
@@ -602,6 +706,7 @@ extern "C" int smol_profile_step(int64_t M, int32_t R, const double *U, const do
     if ((rc = get_roots(p->dev, &r))) return rc;
     if ((rc = alloc_integ(p))) return rc;
     hipStream_t s = (hipStream_t)stream;
+    if ((rc = plan_enter(p, s))) return rc;
     const IntegDev I = integ_dev(p, r);
     IntegCtl &c = *p->host;
     memset(&c, 0, sizeof(c));
@@ -649,6 +754,7 @@ extern "C" int smol_profile_step(int64_t M, int32_t R, const double *U, const do
         ms_out[k] = t / (float)iters;
     }
     for (auto &e : ev) HIP_TRY(hipEventDestroy(e));
+    plan_leave_sync(p);
     return SMOL_OK;
 }
 

@@ -42,7 +42,7 @@ def test_validation_before_device(lib):
     p = ctypes.c_void_p(16)
     assert lib.smol_rhs(0, 3, p, p, 0.0, p, ctypes.c_void_p(32), 0, None) == -1
     assert lib.smol_rhs(10, 0, p, p, 0.0, p, ctypes.c_void_p(32), 0, None) == -1
-    assert lib.smol_rhs(10, 17, p, p, 0.0, p, ctypes.c_void_p(32), 0, None) == -1
+    assert lib.smol_rhs(10, 33, p, p, 0.0, p, ctypes.c_void_p(32), 0, None) == -1
     assert lib.smol_rhs(10, 3, p, p, -1.0, p, ctypes.c_void_p(32), 0, None) == -1
     assert lib.smol_rhs(10, 3, p, p, float("nan"), p, ctypes.c_void_p(32), 0, None) == -1
     assert lib.smol_rhs(10, 3, None, p, 0.0, p, ctypes.c_void_p(32), 0, None) == -1

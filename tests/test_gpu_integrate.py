@@ -2,6 +2,8 @@
 
 Bars: trajectory max-norm relative error <= 1e-6 at t_end; with the same
 controller the step sequence matches the oracle's (times to 1e-9)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -154,6 +156,62 @@ def test_repeatable(smol):
     a, sa = smol.integrate(t(U), t(V), lam, t(n0), 20.0, 1e-6, 1e-12, method="bs3")
     b, sb = smol.integrate(t(U), t(V), lam, t(n0), 20.0, 1e-6, 1e-12, method="bs3")
     assert sa == sb and np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def window_against_oracle(smol, U, V, lam, t_end, fixture, precision):
+    """The first 16 DP5 attempts (rtol 1e-6, atol 1e-12, monodisperse start)
+    against an oracle window stored by tests/golden/make_oracle_windows.py:
+    identical accept / reject decisions, t and h to 1e-6, the error norms to
+    1e-5 where they exceed round-off level (1e-6), the end state to 1e-7
+    (max-norm relative).  From the monodisperse
+    start almost every entry is far below atol, where the weighted norm
+    weighs the transform's round-off (relative to the largest entries) by
+    1 / atol: err differs from the direct sums' by ~1e-8 (FP64) to ~1e-7
+    (float-float) relative, and the controller carries that into h."""
+    import torch
+    ref = np.load(os.path.join(GOLDEN, fixture))
+    rlog = ref["log"]
+    M = U.shape[1]
+    log = torch.zeros((64, 9), dtype=torch.float64, device="cuda:0")
+    out, st = smol.integrate(t(U), t(V), lam, t(W.monodisperse(M)), t_end, 1e-6, 1e-12,
+                             method="dp5", precision=precision, max_steps=16, log=log)
+    say("gpu", st, "oracle counts", ref["counts"])
+    assert st["status"] == smol.EMAXSTEPS
+    assert [st["n_rhs"], st["n_accept"], st["n_reject"]] == list(ref["counts"])
+    g = log.cpu().numpy()[:16]
+    np.testing.assert_array_equal(g[:, 3], rlog[:, 3])
+    np.testing.assert_allclose(g[:, 0], rlog[:, 0], rtol=1e-6)
+    np.testing.assert_allclose(g[:, 1], rlog[:, 1], rtol=1e-6)
+    # the norm itself where it is not at round-off level (the first steps
+    # from the monodisperse start have err ~ 1e-13)
+    ok = rlog[:, 2] > 1e-6
+    np.testing.assert_allclose(g[ok, 2], rlog[ok, 2], rtol=1e-5)
+    err = normwise(out.cpu().numpy(), ref["n"])
+    say(f"{fixture} ({precision}): t = {st['t']:.4e}, end state error {err:.2e}")
+    assert err < 1e-7
+    return err
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32x2"])
+def test_single_large_window_matches_oracle(smol, precision):
+    """The single-large instance (M = 65536, a = 0.45, lam = 0.005) and the
+    precision workload's first instance: the first 16 attempts against the
+    oracle's integrator (about 100 direct O(M^2 R) right-hand sides)."""
+    c = W.WORKLOADS["single-large"]
+    U, V, lam, _ = W.workload_instance("single-large")
+    window_against_oracle(smol, U, V, lam, c["t_end"], "single_large_dp5_w16.npz", precision)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32x2"])
+def test_precision_rank4_window_matches_oracle(smol, precision):
+    """The precision workload's rank-4 product kernel (a = 0.3, lam = 0.02)."""
+    p = W.WORKLOADS["precision"]
+    U, V = W.product_rank4(p["M"], p["a"])
+    window_against_oracle(smol, U, V, p["lam"], p["t_eval"], "precision_rank4_dp5_w16.npz",
+                          precision)
 
 
 def test_config2_full_run_properties(smol):

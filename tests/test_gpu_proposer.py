@@ -87,34 +87,65 @@ def test_training_reduces_loss(smol):
 
 
 def test_dataset_rows_match_oracle_features(smol):
-    """Features of the decision after attempt j equal the oracle's features of
-    the state reached after attempt j (run again with max_steps = j+1); the
-    target is the hindsight log step ratio less PI's log factor."""
+    """Training rows from a logged GPU run equal the oracle's rows built from
+    the same log (features to FP32 rounding, targets to FP32 accuracy), and
+    the features of the decision after attempt j equal the oracle's features
+    of the state reached after attempt j (run again with max_steps = j+1)."""
     import torch
     M = 800
     U, V = W.brownian_rank3(M, 0.4)
     n0 = W.monodisperse(M)
     log = torch.zeros((2000, 9), dtype=torch.float64, device="cuda:0")
-    _, st = smol.integrate(t(U), t(V), 0.02, t(n0), 20.0, 1e-6, 1e-12, method="dp5", log=log)
+    _, st = smol.integrate(t(U), t(V), 0.02, t(n0), 20.0, 1e-6, 1e-12, method="dp5", log=log,
+                           h0=0.5)
     rows = st["n_accept"] + st["n_reject"]
+    assert st["n_reject"] > 0
     X, tg = smol.proposer_dataset(log, rows, "dp5")
     L = log.cpu().numpy()[:rows]
+    Xo, To = oracle.proposer_dataset(L, 5, err_target=0.8)
+    assert X.shape[0] == Xo.shape[0] > 0
+    np.testing.assert_allclose(X.cpu().numpy(), Xo, rtol=2e-7, atol=1e-7)
+    assert np.abs(tg.cpu().numpy() - To).max() < 2e-6
     # rows: accepted attempts with a successor that did not follow a rejection
     acc = [j for j in range(rows - 1) if L[j, 3] == 1 and (j == 0 or L[j - 1, 3] == 1)]
     assert X.shape[0] == len(acc)
     for r, j in list(enumerate(acc))[5::7][:6]:
         nj, sj = smol.integrate(t(U), t(V), 0.02, t(n0), 20.0, 1e-6, 1e-12, method="dp5",
-                                max_steps=j + 1)
+                                max_steps=j + 1, h0=0.5)
         hist = [L[j - q, 2] for q in range(4) if j - q >= 0]
         ref = oracle.features(nj.cpu().numpy(), L[j, 1], hist)
         np.testing.assert_allclose(X[r].cpu().numpy(), ref, rtol=2e-6, atol=2e-7)
-        # hindsight log step ratio, less the PI log factor the run applied
-        want = np.clip(np.log(L[j + 1, 1] / L[j, 1]) + np.log(0.8 / L[j + 1, 2]) / 5,
-                       np.log(0.2), np.log(10))
-        prev = [L[i, 2] for i in range(j) if L[i, 3] == 1]
-        err_prev = max(prev[-1], 1e-4) if prev else 1.0
-        pi = np.log(np.clip(0.9 * L[j, 2] ** -0.14 * err_prev ** 0.08, 0.2, 10.0))
-        assert abs(tg[r].item() - (want - pi)) < 1e-5
+
+
+@pytest.mark.parametrize("seed,b3", [(21, 0.0), (22, 0.3)])
+def test_learned_decisions_match_oracle(smol, seed, b3):
+    """Every step the learned controller takes in a logged GPU run equals the
+    oracle's learned factor exp(clamp(log PI + network(features))) at that
+    decision (FP32 network on the GPU, FP64 in the oracle); decisions after a
+    rejection are PI's."""
+    import torch
+    p = init_params(seed)
+    p[-1] = b3
+    smol.proposer_set(f32(p))
+    M = 3000
+    U, V = W.brownian_rank3(M, 0.35)
+    n0 = W.exponential_start(M, 4.0)
+    log = torch.zeros((6000, 9), dtype=torch.float64, device="cuda:0")
+    _, st = smol.integrate(t(U), t(V), 0.01, t(n0), 40.0, 1e-6, 1e-12, method="dp5",
+                           controller="learned", log=log)
+    rows = st["n_accept"] + st["n_reject"]
+    L = log.cpu().numpy()[:rows]
+    say(f"learned run seed {seed} b3 {b3}: {st}")
+    assert st["status"] == 0 and rows < 6000
+    want = oracle.learned_steps(p.astype(np.float32).astype(np.float64), L, 5)
+    js = [j for j in range(rows - 2) if np.isfinite(want[j])]  # last successor clipped to t_end
+    assert len(js) >= 10
+    got = L[np.array(js) + 1, 1] / L[js, 1]
+    rel = np.abs(got / want[js] - 1.0)
+    say(f"  {len(js)} learned decisions, max relative difference {rel.max():.2e}")
+    assert rel.max() < 2e-5
+    assert st["n_fallback"] == sum(1 for j in range(rows)
+                                   if L[j, 3] == 1 and j > 0 and L[j - 1, 3] != 1)
 
 
 def test_bad_proposer_falls_back_to_pi(smol):
