@@ -593,13 +593,16 @@ def bench_learned(args, smol, W, torch, dev):
 
 def bench_sweep_learned(args, smol, W, torch, dev):
     """The batched form with the trained proposer against the plain
-    single-instance PI solver: the 256 sweep instances of the batched
-    workload (seed 0, held out from the training seed), DP5(4) (the pair the
-    proposer was trained on), rtol 1e-6, atol 1e-12, t = 0 -> 1e3.  Batched
-    runs with the learned controller and with PI are timed whole; the
-    single-instance PI runs on every 32nd instance, extrapolated to all 256.
-    Accuracy: on those sampled instances both batched end states are
-    compared with tight single runs (rtol 1e-10, atol 1e-16)."""
+    single-instance PI solver, each at its time-to-t_end at 1e-6 relative
+    error: the 256 sweep instances of the batched workload (seed 0, held out
+    from the training seed), DP5(4) (the pair the proposer was trained on),
+    atol 1e-12, t = 0 -> 1e3.  For each form the loosest rtol in 1e-6, 3e-7,
+    1e-7, 3e-8 whose end states on every 32nd instance are within 1e-6
+    (max-norm relative) of tight single runs (rtol 1e-10, atol 1e-16) is
+    taken, as for the single-large workload.  Batched runs are timed whole;
+    single-instance PI runs on the sampled instances, extrapolated to all 256
+    (a batched instance equals its single run bitwise, so both PI forms meet
+    the bar at the same rtol)."""
     c = W.WORKLOADS["batched-sweep"]
     t_end = c["t_end"]
     draws = W.batch_draws(c["n_inst"], seed=c["seed"])
@@ -609,38 +612,50 @@ def bench_sweep_learned(args, smol, W, torch, dev):
         insts.append(dict(U=torch.from_numpy(U).to(dev), V=torch.from_numpy(V).to(dev), lam=lam,
                           n0=torch.from_numpy(n0).to(dev), t_end=t_end, rtol=c["rtol"],
                           atol=c["atol"]))
-    res, outs = {}, {}
-    for ctrl in ("pi", "learned"):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        o, stats = smol.integrate_batch(insts, method="dp5", controller=ctrl)
-        torch.cuda.synchronize()
-        outs[ctrl] = o
-        res["batched_" + ctrl] = {
-            "time_s": time.perf_counter() - t0,
-            "n_rhs": sum(st["n_rhs"] for st in stats),
-            "n_reject": sum(st["n_reject"] for st in stats),
-            "all_ok": all(st["status"] == 0 for st in stats)}
     sample = list(range(0, len(insts), 32))
+    refs = {}
+    for i in sample:
+        d = insts[i]
+        refs[i], _ = smol.integrate(d["U"], d["V"], d["lam"], d["n0"], t_end, 1e-10, 1e-16,
+                                    method="dp5", raise_on_error=True)
+
+    def err_on_sample(outs):
+        return max(((outs[i] - refs[i]).abs().max() / refs[i].abs().max()).item() for i in sample)
+
+    res = {}
+    for ctrl in ("pi", "learned"):
+        for rtol in (1e-6, 3e-7, 1e-7, 3e-8):
+            run = [dict(d, rtol=rtol) for d in insts]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            o, stats = smol.integrate_batch(run, method="dp5", controller=ctrl)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            e = err_on_sample(o)
+            res["batched_" + ctrl] = {
+                "rtol": rtol, "time_s": dt, "max_rel_err_vs_tight_on_sample": e,
+                "n_rhs": sum(st["n_rhs"] for st in stats),
+                "n_reject": sum(st["n_reject"] for st in stats),
+                "rhs_evals_per_s": sum(st["n_rhs"] for st in stats) / dt,
+                "all_ok": all(st["status"] == 0 for st in stats)}
+            print(f"bench: sweep batched {ctrl} rtol {rtol:g}: {res['batched_' + ctrl]}",
+                  file=sys.stderr, flush=True)
+            if e <= 1e-6:
+                break
+    rtol_pi = res["batched_pi"]["rtol"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in sample:
         d = insts[i]
-        smol.integrate(d["U"], d["V"], d["lam"], d["n0"], t_end, d["rtol"], d["atol"],
+        smol.integrate(d["U"], d["V"], d["lam"], d["n0"], t_end, rtol_pi, d["atol"],
                        method="dp5", raise_on_error=True)
     torch.cuda.synchronize()
-    res["single_pi_extrapolated_s"] = (time.perf_counter() - t0) * len(insts) / len(sample)
-    err = {"pi": 0.0, "learned": 0.0}
-    for i in sample:
-        d = insts[i]
-        ref, _ = smol.integrate(d["U"], d["V"], d["lam"], d["n0"], t_end, 1e-10, 1e-16,
-                                method="dp5", raise_on_error=True)
-        for ctrl in err:
-            e = ((outs[ctrl][i] - ref).abs().max() / ref.abs().max()).item()
-            err[ctrl] = max(err[ctrl], e)
-    res["max_rel_err_vs_tight_on_sample"] = err
-    res["speedup_batched_learned_vs_single_pi"] = (res["single_pi_extrapolated_s"]
+    res["single_pi"] = {"rtol": rtol_pi,
+                        "time_s_extrapolated": (time.perf_counter() - t0) * len(insts) / len(sample)}
+    res["speedup_batched_learned_vs_single_pi"] = (res["single_pi"]["time_s_extrapolated"]
                                                   / res["batched_learned"]["time_s"])
+    res["speedup_batched_pi_vs_single_pi"] = (res["single_pi"]["time_s_extrapolated"]
+                                             / res["batched_pi"]["time_s"])
     print(f"bench: batched sweep: {res}", file=sys.stderr, flush=True)
     return res
 

@@ -123,8 +123,9 @@ def test_two_source_workload(smol):
 def test_two_source_workload_free_molecular(smol):
     """The same workload with Sec. 3.1's free-molecular kernel, which has no
     exact low-rank form: factors from smol_lowrank (tol 1e-12), then each
-    scheme at tol 1e-6 to t = 1000; time, right-hand sides and the mass held
-    (against the mass the sources inject) are reported."""
+    scheme at tol 1e-6 to t = 100 (to t = 1000 each run takes 40-50 s: the
+    step is stability-limited, about 6e5 evaluations); time, right-hand sides
+    and the mass held against the mass the sources inject are reported."""
     import torch
     M, p = 32768, 0.05
     U, V, est = smol.lowrank(M, "free_molecular", tol=1e-12)
@@ -135,7 +136,7 @@ def test_two_source_workload_free_molecular(smol):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         atol = 0.0 if ctrl != "pi" else 1e-12
-        out, st = smol.integrate(U, V, 0.0, n0, 1000.0, 1e-6, atol, method=method,
+        out, st = smol.integrate(U, V, 0.0, n0, 100.0, 1e-6, atol, method=method,
                                  controller=ctrl, source=P, max_steps=2000000)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -143,4 +144,4 @@ def test_two_source_workload_free_molecular(smol):
         s = np.arange(1, M + 1)
         mass = float(np.sum(s * out.cpu().numpy()))
         say(f"free-molecular {method}/{ctrl} tol 1e-6: {dt:.2f} s / {st['n_rhs']} RHS, "
-            f"mass {mass:.6g} (sources inject {1000.0 * (1 + 100 * p):.6g})")
+            f"mass {mass:.6g} (sources inject {100.0 * (1 + 100 * p):.6g})")
