@@ -5,6 +5,7 @@
 
 #define SMOL_WG 256            // threads per workgroup (4 wave64)
 #define SMOL_WAVES (SMOL_WG / 64)
+#define SMOL_NUM_CU 256        // compute units of an MI355X (8 XCDs x 32)
 #define SMOL_MAX_R 32
 #define SMOL_LOG_TW 10         // unit-root tables have 2^10 entries
 #define SMOL_TW (1 << SMOL_LOG_TW)

@@ -21,8 +21,9 @@
 // FFT of length L = N1 * N2 in four steps (index n = N2 n1 + n2, frequency
 // k = k1 + N1 k2), run as three phases separated by grid-wide barriers:
 //   A  column pass: per column n2, DFT over n1 (length N1; rows n1 >= N1/2
-//      are zero padding), times W_L^{n2 k1}; staged through LDS and stored
-//      row-major Z[k1][n2] in segments of several columns.
+//      are zero padding), times W_L^{n2 k1}; stored column by column
+//      (Z[n2][k1]: one contiguous run per column; phase B reads its rows
+//      with stride N1, neighbouring row pairs sharing cache lines).
 //   B  per row pair {k1, N1-k1}: DFT over n2 (length N2) of every rank's two
 //      rows, the spectral product P (rows k1 and N1-k1 hold k and L-k), then
 //      the inverse DFT over k2 times W_L^{-a k1}, with columns a and a+N2/2
@@ -30,7 +31,7 @@
 //   C  per packed column: inverse DFT over k1 (length N1) gives
 //      L (c[a + N2 b] + i c[a + N2/2 + N2 b]); the finish computes S and the
 //      caller's fused epilogue (stage state, error norm, ...), spread over
-//      the whole workgroup.
+//      the whole workgroup (or over two workgroups, one per real column).
 //
 // Layouts of the per-size vectors (state, stages, U, V): natural (size s at
 // index s-1) or transposed, where index idx = N2 n1 + n2 < L/2 lives at
@@ -321,7 +322,6 @@ struct PhaseB {
             twi.load(g, P.rt);
             step_twiddles<F::E, true>(P.rt, P.logL, (uint32_t)(slot ? k1p : k1), g, F::G, t4);
         }
-        for (int k2 = tid; k2 < N2; k2 += NT) P1[k2] = czero<C>();
         for (int a0 = 0; a0 < P.R; a0 += AL_PER_ROUND) {
             const int na = min(AL_PER_ROUND, P.R - a0);
             // slot 2m holds rank a0+m row k1, slot 2m+1 its row N1-k1
@@ -341,26 +341,28 @@ struct PhaseB {
                 }
             }
             __syncthreads();
+            const bool last = a0 + AL_PER_ROUND >= P.R;
             for (int k2 = tid; k2 < N2; k2 += NT) {
                 // partner of (k1, k2) is (k1p, k2p)
                 const int k2p = (k1 == 0) ? ((N2 - k2) & (N2 - 1)) : (N2 - 1 - k2);
-                C acc = P1[k2];
+                C acc = a0 ? P1[k2] : czero<C>();
                 for (int m = 0; m < na; ++m) {
                     const C a = rows[(2 * m) * N2 + k2];
                     const C b = rows[(2 * m + (single ? 0 : 1)) * N2 + k2p];
                     acc = spec_term(acc, a, b);
                 }
-                P1[k2] = acc;
+                if (last) {
+                    // divide by 4i: x / (4i) = (x.y, -x.x) / 4; partner row
+                    // by conjugate reversal
+                    const C q = div4i(acc);
+                    P1[k2] = q;
+                    if (!single) P2[N2 - 1 - k2] = cconj(q);
+                } else {
+                    P1[k2] = acc;
+                }
             }
             __syncthreads();
         }
-        // divide by 4i: x / (4i) = (x.y, -x.x) / 4; partner row by conjugate reversal
-        for (int k2 = tid; k2 < N2; k2 += NT) {
-            const C q = div4i(P1[k2]);
-            P1[k2] = q;
-            if (!single) P2[N2 - 1 - k2] = cconj(q);
-        }
-        __syncthreads();
         // inverse DFT over k2 of rows k1 (slot 0) and N1-k1 (slot 1)
         if (inv) {
             const int krow = slot ? k1p : k1;
@@ -412,23 +414,53 @@ struct PhaseC {
     static constexpr int NT = 64 * W;
     static constexpr int HALF = N2 / 2;
     static constexpr int COLS = (F::B < HALF) ? F::B : HALF;  // packed columns per unit
-    static constexpr int NPOS = COLS * N1;                     // outputs per unit
+    // Workgroups per unit.  A packed column holds two real columns (real and
+    // imaginary part); where a unit has one packed column and four waves and
+    // the units alone would leave compute units idle (N2 / 2 < 256), its two
+    // real columns go to two workgroups, each running the unit's inverse
+    // transform itself: twice the workgroups (a full chip at L = 2^17) for
+    // one more packed-column read each.
+    static constexpr int S = (COLS == 1 && W == 4 && HALF < SMOL_NUM_CU) ? 2 : 1;
+    static constexpr int NPOS = COLS * N1 / S;                 // outputs per workgroup
     static constexpr int PP = (NPOS + NT - 1) / NT;            // per thread
     static constexpr int LDS = 64 * F::E;                      // wave 0 scratch
+    static constexpr int NCOL = 2 * COLS / S;                  // real columns per workgroup
     // fused with the next column pass: W waves of scratch + the next stage
-    // state of the unit's 2 COLS columns (doubles)
-    // (2 COLS columns x N1/2 rows of doubles = COLS N1 / 2 sixteen-byte entries)
-    static constexpr int LDS_FUSE = W * 64 * F::E + COLS * N1 / 2;
-    static __host__ __device__ int units() { return HALF / COLS; }
+    // state of the workgroup's NCOL columns (doubles)
+    // (NCOL columns x N1/2 rows of doubles = NCOL N1 / 4 sixteen-byte entries)
+    static constexpr int LDS_FUSE = W * 64 * F::E + NCOL * N1 / 4;
+    static __host__ __device__ int units() { return HALF / COLS * S; }
     static __host__ __device__ int jobs() { return units(); }
+
+    // Output e of workgroup `unit` (0 <= e < NPOS): row b of the unit's
+    // packed column f, real (hh = 0) or imaginary part; its local column
+    // (NCOL of them) orders the fused column pass.  Sizes m + 2 with
+    // m = ac + hh HALF + N2 b, ac = cu COLS + f the packed column.
+    __device__ static void decode(int unit, int e, int &cu, int &b, int &hh, int &f, int &lc)
+    {
+        cu = unit / S;
+        b = e % (N1 / 2);
+        if constexpr (S == 1) {
+            hh = (e / (N1 / 2)) & 1;
+            f = e / N1;
+            lc = hh * COLS + f;
+        } else {
+            hh = unit % S;
+            f = e / (N1 / 2);
+            lc = f;
+        }
+    }
+    // the workgroup that computes size 1 (the last unit's imaginary half)
+    __device__ static bool owns_size1(int unit) { return unit == units() - 1; }
 
     static constexpr int KMAX = 6;  // stage vectors an epilogue combines
     static constexpr int RPRE = 4;  // ranks whose U, V are prefetched
 
-    // FUSE (stage epilogue only): the unit's outputs y_{i+1} fill exactly the
-    // 2 COLS columns ac+1 and ac+1+N2/2 of the next column pass (the last
-    // unit also owns column 0: it computes size 1 and wraps onto row b+1),
-    // so the workgroup runs that pass itself and writes the next spectra.
+    // FUSE (stage epilogue only): a workgroup's outputs y_{i+1} fill exactly
+    // its NCOL columns ac+1 and/or ac+1+N2/2 of the next column pass (the
+    // workgroup that computes size 1 also owns column 0: its imaginary half
+    // wraps onto row b+1), so the workgroup runs that pass itself and writes
+    // the next spectra.
     struct ColPre;
     struct Early;
 
@@ -463,8 +495,9 @@ struct PhaseC {
             sz[j] = 0;
             yv[j] = nv[j] = sv[j] = 0.0;
             if (e < NPOS) {
-                const int b = e % (N1 / 2), hh = (e / (N1 / 2)) & 1, f = e / N1;
-                const int64_t m = unit * COLS + f + hh * HALF + (int64_t)N2 * b;
+                int cu, b, hh, f, lc;
+                decode(unit, e, cu, b, hh, f, lc);
+                const int64_t m = cu * COLS + f + hh * HALF + (int64_t)N2 * b;
                 if (m <= M - 2) {
                     const int64_t q = pos_of(P, m + 1);
                     qv[j] = q;
@@ -493,7 +526,7 @@ struct PhaseC {
         double wred[RPRE];
 #pragma unroll
         for (int a = 0; a < RPRE; ++a) wred[a] = a < rp ? P.red[4 * a] : 0.0;
-        const bool last = unit == units() - 1;
+        const bool last = owns_size1(unit);
         double S1 = 0.0, y1 = 0.0, n1v = 0.0, k1v[KMAX];
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) k1v[k] = 0.0;
@@ -540,7 +573,8 @@ struct PhaseC {
             yn[j] = 0.0;
             if (qv[j] >= 0) {
                 const int e = tid + j * NT;
-                const int b = e % (N1 / 2), hh = (e / (N1 / 2)) & 1, f = e / N1;
+                int cu, b, hh, f, lc;
+                decode(unit, e, cu, b, hh, f, lc);
                 const C val = lds[f * (N1 / 2) + b];
                 const double c = (hh ? im_d(val) : re_d(val)) * invL;
                 double dsum = 0.0;
@@ -564,13 +598,14 @@ struct PhaseC {
             for (int j = 0; j < PP; ++j) {
                 if (qv[j] >= 0) {
                     const int e = tid + j * NT;
-                    const int b = e % (N1 / 2), hh = (e / (N1 / 2)) & 1, f = e / N1;
-                    const int wrap = (unit * COLS + f + 1 + hh * HALF) == N2;
+                    int cu, b, hh, f, lc;
+                    decode(unit, e, cu, b, hh, f, lc);
+                    const int wrap = (cu * COLS + f + 1 + hh * HALF) == N2;
                     const int n1 = b + wrap;
-                    if (n1 < N1 / 2) ycol[(hh * COLS + f) * (N1 / 2) + n1] = yn[j];
+                    if (n1 < N1 / 2) ycol[lc * (N1 / 2) + n1] = yn[j];
                 }
             }
-            if (mono) ycol[(2 * COLS - 1) * (N1 / 2)] = yn1;
+            if (mono) ycol[(NCOL - 1) * (N1 / 2)] = yn1;
         }
         if constexpr (FUSE) {
             // the next column pass first: its spectra are the bulk of the
@@ -652,12 +687,14 @@ struct PhaseC {
         ColPre pre;                // FUSE: this wave slot's first column-pass transform
     };
 
+    // column-pass transform `job` of workgroup `unit`: local column jj (as
+    // decode() numbers them), rank al, global column n2
     __device__ static void col_job(const RhsPlanDev &P, int unit, int job, int &jj, int &al, int &n2)
     {
-        jj = job % (2 * COLS);
-        al = job / (2 * COLS);
-        const int hh = jj / COLS, fc = jj % COLS;
-        n2 = (unit * COLS + fc + 1 + hh * HALF) & (N2 - 1);
+        jj = job % NCOL;
+        al = job / NCOL;
+        const int hh = S == 1 ? jj / COLS : unit % S, fc = S == 1 ? jj % COLS : jj;
+        n2 = ((unit / S) * COLS + fc + 1 + hh * HALF) & (N2 - 1);
     }
 
     __device__ static void col_load(const RhsPlanDev &P, int unit, int job, ColPre &pre)
@@ -691,11 +728,11 @@ struct PhaseC {
         const int lane = lane_id(), w = wave_id();
         if constexpr (FUSE) {
             const int job = w * F::B + lane / F::G;
-            if (job < 2 * COLS * P.R) col_load(P, unit, job, e.pre);
+            if (job < NCOL * P.R) col_load(P, unit, job, e.pre);
         }
         if (w == 0) {
             const int f = lane / F::G, g = lane % F::G;
-            const int ac = unit * COLS + f;
+            const int ac = (unit / S) * COLS + f;
             e.tw.load(g, P.rt);
             const C *Qp = (const C *)P.Qp;
 #pragma unroll
@@ -710,7 +747,7 @@ struct PhaseC {
         const int lane = lane_id(), w = wave_id();
         const int f = lane / F::G, g = lane % F::G;
         const int64_t M = P.M;
-        const int nj = 2 * COLS * P.R;
+        const int nj = NCOL * P.R;
         for (int r0 = 0; r0 < nj; r0 += W * F::B) {
             const int job = r0 + w * F::B + f;
             if (job < nj) {
