@@ -84,6 +84,27 @@ def test_variant_rhs_large(smol, restore, logL):
         assert e_base < 1e-12 and e_or < TOL_RHS, (sched, e_base, e_or)
 
 
+@pytest.mark.parametrize("logL,split,whole", [(15, 2, 3), (16, 2, 3), (17, 0, 1)])
+def test_split_finish_bitwise(smol, restore, logL, split, whole):
+    """Phase C with two workgroups per packed column (four waves, one packed
+    column per unit) computes exactly what one eight-wave workgroup per
+    packed column does: the same inverse transform and finish per output,
+    only spread over twice the workgroups."""
+    import torch
+    L = 2 ** logL
+    for M in (L // 2 - 1234, L // 2 + 1):
+        for R in (3, 5):
+            U, V = W.random_factors(M, R, seed=logL + R)
+            n = W.random_state(M, seed=M)
+            out = []
+            for v in (whole, split):
+                smol.set_schedule(logL, [0, 0, v])
+                out.append(smol.rhs(t(U), t(V), 0.01, t(n)))
+            same = bool(torch.equal(out[0], out[1]))
+            say(f"logL={logL} M={M} R={R}: C variant {split} bitwise equal to {whole}: {same}")
+            assert same
+
+
 @pytest.mark.parametrize("logL", [13, 17])
 def test_variant_integration(smol, restore, logL):
     """DP5 runs under every variant (fused finish + column pass included)
