@@ -84,6 +84,12 @@ def step_bytes(M, R, L):
             "int_c_last": 8 * L + 64 * M + 8 * M * R}
 
 
+def min_bytes(M, R):
+    """Compulsory HBM bytes of one right-hand side (FP64): read n, U and V
+    once and write S, with no intermediate spectra."""
+    return 8 * M * (2 + 2 * R)
+
+
 # launches of each stage kernel per DP5(4) attempt (stages 2..7)
 STEP_LAUNCHES = {"int_a": 1, "int_b": 6, "int_c_fused": 5, "int_c_last": 1}
 
@@ -99,10 +105,12 @@ def cpu_model():
     return "unknown CPU"
 
 
-def cpu_baseline(U, V, lam, n0, per_step_rhs):
+def cpu_baseline(U, V, lam, n0, per_step_rhs, run_rhs=None):
     """The FP64 oracle (plain O(M^2) direct sums) timed on the host: one full
     right-hand side at the start state on all host threads (up to 16) and
-    one on a single thread, converted to DP5 steps/s."""
+    one on a single thread, converted to DP5 steps/s; with run_rhs (the GPU
+    run's evaluations to t_end) also the oracle's time to t_end, extrapolated
+    as run_rhs times its seconds per right-hand side."""
     import oracle
     threads = min(16, os.cpu_count() or 1)
     oracle.lib()
@@ -113,14 +121,18 @@ def cpu_baseline(U, V, lam, n0, per_step_rhs):
     oracle.rhs(U, V, lam, n0, threads=1)
     dt1 = time.perf_counter() - t0
     model = cpu_model()
-    return {"value": 1.0 / (per_step_rhs * dt), "unit": "accepted steps/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"one direct O(M^2 R) right-hand side at M={n0.size} "
-                      f"({dt:.2f} s on {threads} threads of {os.cpu_count()} x {model}), "
-                      f"times {per_step_rhs} per DP5 step",
-            "rhs_evals_per_s": 1.0 / dt,
-            "single_thread": {"value": 1.0 / (per_step_rhs * dt1), "rhs_evals_per_s": 1.0 / dt1,
-                              "cores": 1, "rhs_s": dt1}}
+    res = {"value": 1.0 / (per_step_rhs * dt), "unit": "accepted steps/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"one direct O(M^2 R) right-hand side at M={n0.size} "
+                     f"({dt:.2f} s on {threads} threads of {os.cpu_count()} x {model}), "
+                     f"times {per_step_rhs} per DP5 step",
+           "rhs_evals_per_s": 1.0 / dt,
+           "single_thread": {"value": 1.0 / (per_step_rhs * dt1), "rhs_evals_per_s": 1.0 / dt1,
+                             "cores": 1, "rhs_s": dt1}}
+    if run_rhs:
+        res["time_to_t_end_extrapolated_s"] = run_rhs * dt
+        res["single_thread"]["time_to_t_end_extrapolated_s"] = run_rhs * dt1
+    return res
 
 
 def plain_small(smol, W, torch, dev):
@@ -279,7 +291,9 @@ def main():
             "stage_kernels_ms_per_attempt": attempt_ms,
             "share_of_stage_kernels": prof[dom] * STEP_LAUNCHES[dom] / attempt_ms,
             "standalone_rhs": {"ms_per_launch": rhs, "alg_bytes": rb,
-                               "frac": rb["rhs"] / (rhs["rhs"] * 1e-3) / HBM_PEAK}}
+                               "frac": rb["rhs"] / (rhs["rhs"] * 1e-3) / HBM_PEAK,
+                               "min_bytes": min_bytes(M, R),
+                               "frac_min_bytes": min_bytes(M, R) / (rhs["rhs"] * 1e-3) / HBM_PEAK}}
 
     line = {
         "metric": "accepted RK steps/s (time-to-t_end at rtol 1e-6), M=2^16 R=3",
@@ -311,8 +325,10 @@ def main():
     # the kernel's rate against a plain copy that moves the same bytes in one launch
     roof["frac_of_copy"] = roof["frac"] / roof["copy_same_footprint"]["frac"]
     line["rhs_precision"] = rhs_precision_times(smol, torch, Ud, Vd, lam, out.clone())
+    # the transform's round-off leaves tiny negative values in the tail; not clamped
+    line["min_n_at_t_end"] = float(out.min().item())
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(U, V, lam, n0, 6)
+        line["cpu_baseline"] = cpu_baseline(U, V, lam, n0, 6, stats[-1]["n_rhs"])
         line["plain_small"] = plain_small(smol, W, torch, dev)
     print(json.dumps(line), flush=True)
 

@@ -34,6 +34,8 @@ def test_byte_counts_at_the_bench_size():
     assert sb["int_c_last"] == packed + 8 * vec + fac          # n_new, n, 5 stages, k7; U
     assert set(bench.STEP_LAUNCHES) == set(sb)
     assert bench.STEP_LAUNCHES["int_b"] == 6  # one row-pair pass per DP5 right-hand side
+    # compulsory bytes: n, U, V read once, S written; 4 MiB at this size
+    assert bench.min_bytes(M, R) == vec + 2 * fac + vec == 4 * 2 ** 20
 
 
 def test_recorded_traffic_follows_the_source_hash(monkeypatch):
