@@ -450,7 +450,8 @@ struct PhaseC {
             lc = f;
         }
     }
-    // the workgroup that computes size 1 (the last unit's imaginary half)
+    // the workgroup that computes size 1: the last unit (with two workgroups
+    // per unit, the one with its imaginary half)
     __device__ static bool owns_size1(int unit) { return unit == units() - 1; }
 
     static constexpr int KMAX = 6;  // stage vectors an epilogue combines
