@@ -10,7 +10,7 @@
 #include "integrate.h"
 
 #define SMOL_HIDDEN __attribute__((visibility("hidden")))
-#define SMOL_GRAPH_ATTEMPTS 4  // step attempts captured per graph
+#define SMOL_GRAPH_ATTEMPTS 16  // step attempts captured per graph
 
 inline int hip_fail(hipError_t e, const char *what)
 {

@@ -374,24 +374,32 @@ __device__ inline void prepare_attempt(IntegCtl &c, bool new_step)
     c.h = tn - c.t;
 }
 
-// Deterministic block reduction of epart rows (fixed strided order, then a
-// fixed tree); every thread receives the totals.
+// Deterministic block reduction of epart rows: each thread sums a fixed
+// stride of rows, the wave butterfly adds the threads of a wave, then the
+// waves are added in order; every thread receives the totals.
 __device__ inline void block_sum_epart(const double *ep, int njobs, double *tot)
 {
-    __shared__ double sh[SMOL_WG][SMOL_EPART];
+    __shared__ double sh[SMOL_WAVES][SMOL_EPART];
     const int tid = threadIdx.x;
     double acc[SMOL_EPART];
+#pragma unroll
     for (int q = 0; q < SMOL_EPART; ++q) acc[q] = 0.0;
     for (int j = tid; j < njobs; j += SMOL_WG)
+#pragma unroll
         for (int q = 0; q < SMOL_EPART; ++q) acc[q] += ep[(int64_t)j * SMOL_EPART + q];
-    for (int q = 0; q < SMOL_EPART; ++q) sh[tid][q] = acc[q];
+#pragma unroll
+    for (int q = 0; q < SMOL_EPART; ++q) acc[q] = wave_sum(acc[q]);
+    if (lane_id() == 0)
+#pragma unroll
+        for (int q = 0; q < SMOL_EPART; ++q) sh[wave_id()][q] = acc[q];
     __syncthreads();
-    for (int off = SMOL_WG / 2; off >= 1; off >>= 1) {
-        if (tid < off)
-            for (int q = 0; q < SMOL_EPART; ++q) sh[tid][q] += sh[tid + off][q];
-        __syncthreads();
+#pragma unroll
+    for (int q = 0; q < SMOL_EPART; ++q) {
+        double a = 0.0;
+#pragma unroll
+        for (int w = 0; w < SMOL_WAVES; ++w) a += sh[w][q];
+        tot[q] = a;
     }
-    for (int q = 0; q < SMOL_EPART; ++q) tot[q] = sh[0][q];
     __syncthreads();
 }
 
