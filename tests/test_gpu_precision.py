@@ -1,6 +1,7 @@
 """Float-float (SMOL_FP32X2) variant: the convolution transforms in hi/lo FP32
 pairs, everything else FP64.  Checked against the FP64 oracle (RHS) and the
-FP64 GPU path (trajectories of the precision workload to t = 1e3)."""
+FP64 GPU path (whole vectors at every transform length up to 2^20;
+trajectories of the precision workload to t = 1e3)."""
 import numpy as np
 import pytest
 
@@ -49,6 +50,25 @@ def test_rhs_fp32x2_full_size(smol, kernel):
     assert err < TOL_RHS and normwise(a, b) < TOL_RHS
 
 
+@pytest.mark.parametrize("M,R", [(131072, 3), (262144, 3), (524288, 3), (65536, 5), (5000, 8)])
+def test_rhs_fp32x2_long_transforms_and_ranks(smol, M, R):
+    """Float-float at transform lengths 2^18 .. 2^20 and at ranks that take
+    several rounds of the row-pair pass: sampled entries against the oracle's
+    direct sums and the whole vector against the FP64 path (which the RHS
+    tests check against the oracle on every entry at M = 5000, 65536 and
+    262144, and on sampled entries at the other lengths)."""
+    U, V = W.random_factors(M, R, seed=M + R)
+    n = W.exponential_start(M, M / 200.0) + 1e-3 * W.random_state(M, seed=R, decay=False) / M
+    a = smol.rhs(t(U), t(V), 0.01, t(n), precision="fp32x2").cpu().numpy()
+    b = smol.rhs(t(U), t(V), 0.01, t(n)).cpu().numpy()
+    idx = np.unique(np.array([0, 1, 2, 3, 77, M // 7, M // 2, M - 2, M - 1]))
+    ref = oracle.rhs_entries(U, V, 0.01, n, idx)
+    err = np.abs(a[idx] - ref).max() / np.abs(a).max()
+    say(f"fp32x2 rhs M={M} R={R}: sampled error vs oracle {err:.2e}, "
+        f"normwise vs FP64 GPU {normwise(a, b):.2e}")
+    assert err < TOL_RHS and normwise(a, b) < TOL_RHS
+
+
 @pytest.mark.parametrize("name,kernel,a,lam", [("rank3", "rank3", 0.45, 0.005),
                                                ("rank4", "rank4", 0.3, 0.02)])
 def test_precision_workload_trajectory(smol, name, kernel, a, lam):
@@ -66,3 +86,21 @@ def test_precision_workload_trajectory(smol, name, kernel, a, lam):
         f"steps {sx['n_accept']} vs {sy['n_accept']}")
     assert sx["status"] == 0 and sy["status"] == 0
     assert err < 1e-6
+
+
+@pytest.mark.parametrize("M", [131072, 262144])
+def test_fp32x2_integration_long_transform(smol, M):
+    """DP5 with float-float convolutions at L = 2^18 and 2^19 (monodisperse
+    start, rank-3 kernel a = 0.45, lam = 0.005, t = 20): within the
+    trajectory bar of the FP64 run, with the same step counts to within
+    two."""
+    U, V = W.brownian_rank3(M, 0.45)
+    n0 = t(W.monodisperse(M))
+    a, sa = smol.integrate(t(U), t(V), 0.005, n0, 20.0, 1e-6, 1e-12, method="dp5",
+                           precision="fp32x2")
+    b, sb = smol.integrate(t(U), t(V), 0.005, n0, 20.0, 1e-6, 1e-12, method="dp5")
+    err = normwise(a.cpu().numpy(), b.cpu().numpy())
+    say(f"fp32x2 DP5 M={M} t=20: accepted {sa['n_accept']} vs {sb['n_accept']}, "
+        f"difference {err:.2e}")
+    assert sa["status"] == 0 and sb["status"] == 0
+    assert abs(sa["n_accept"] - sb["n_accept"]) <= 2 and err < 1e-6
