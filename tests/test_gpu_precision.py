@@ -64,9 +64,13 @@ def test_rhs_fp32x2_long_transforms_and_ranks(smol, M, R):
     idx = np.unique(np.array([0, 1, 2, 3, 77, M // 7, M // 2, M - 2, M - 1]))
     ref = oracle.rhs_entries(U, V, 0.01, n, idx)
     err = np.abs(a[idx] - ref).max() / np.abs(a).max()
-    say(f"fp32x2 rhs M={M} R={R}: sampled error vs oracle {err:.2e}, "
-        f"normwise vs FP64 GPU {normwise(a, b):.2e}")
-    assert err < TOL_RHS and normwise(a, b) < TOL_RHS
+    # sizes s >= 2 on their own scale: S_1 (mostly the FP64 reductions) is
+    # the largest entry here and would hide the convolution's error
+    e2 = np.abs(a[idx[idx > 0]] - ref[idx > 0]).max() / np.abs(b[1:]).max()
+    n2 = normwise(a[1:], b[1:])
+    say(f"fp32x2 rhs M={M} R={R}: sampled error vs oracle {err:.2e} (sizes >= 2: {e2:.2e}), "
+        f"normwise vs FP64 GPU {normwise(a, b):.2e} (sizes >= 2: {n2:.2e})")
+    assert err < TOL_RHS and e2 < TOL_RHS and n2 < TOL_RHS
 
 
 @pytest.mark.parametrize("name,kernel,a,lam", [("rank3", "rank3", 0.45, 0.005),
