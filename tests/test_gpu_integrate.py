@@ -236,3 +236,24 @@ def test_config2_full_run_properties(smol):
     # terms; round-off is relative to those terms, so scale by the loss term
     loss = (1 + lam) * np.abs(n) * np.abs(U.T @ (V @ n))
     assert np.abs(S[idx] - ref).max() / loss.max() < 1e-10
+
+
+def test_largest_size_run(smol):
+    """M = 2^19 + 1 (transform length 2^20, the largest): DP5 from the
+    monodisperse start to t = 5 ends with status OK, conserves mass (the
+    distribution is far from M, so the truncation flux is nil) and agrees
+    with the same run at M = 4096 on the sizes both hold, to the trajectory
+    bar (the norms average over different M, so the step sizes differ)."""
+    res = {}
+    for M in (4096, 2 ** 19 + 1):
+        U, V = W.brownian_rank3(M, 0.4)
+        out, st = smol.integrate(t(U), t(V), 0.01, t(W.monodisperse(M)), 5.0, 1e-6, 1e-12,
+                                 method="dp5")
+        say(f"M={M}: {st}")
+        assert st["status"] == 0 and st["t"] == 5.0
+        n = out.cpu().numpy()
+        mass = np.sum(np.arange(1, M + 1) * n)
+        assert abs(mass - 1.0) < 1e-10, mass
+        res[M] = n
+    a, b = res[4096], res[2 ** 19 + 1][:4096]
+    assert normwise(b, a) < 1e-6

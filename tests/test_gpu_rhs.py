@@ -61,11 +61,12 @@ def test_rhs_full_size_every_entry(smol, M, R, a):
 
 
 @pytest.mark.parametrize("M", [5000, 65536])
-@pytest.mark.parametrize("R", [2, 5, 8, 16])
+@pytest.mark.parametrize("R", [2, 5, 8, 16, 32])
 def test_rhs_ranks_beyond_prefetch(smol, M, R):
-    """Ranks 2 (the paper's Brownian kernel without constant term) and 5..16:
-    the row-pair pass takes several rounds of ranks and the finish reads the
-    ranks beyond its prefetched four, under the installed schedule."""
+    """Ranks 2 (the paper's Brownian kernel without constant term) and 5..32
+    (32 is the largest the library takes): the row-pair pass takes several
+    rounds of ranks and the finish reads the ranks beyond its prefetched
+    four, under the installed schedule."""
     say(f"rhs rank M={M} R={R}")
     U, V = W.random_factors(M, R, seed=1000 * R + M % 997)
     n = _spread_state(M)
@@ -74,6 +75,30 @@ def test_rhs_ranks_beyond_prefetch(smol, M, R):
     err = normwise(got, ref)
     say(f"  normwise error {err:.2e}")
     assert err < TOL
+
+
+def test_rhs_largest_size(smol):
+    """M = 2^19 + 1, the largest size (transform length 2^20): sampled
+    entries against the oracle, ragged tail included; one size more is
+    refused (SMOL_EUNSUPPORTED) by smol_rhs and smol_integrate."""
+    M = 2 ** 19 + 1
+    U, V = W.random_factors(M, 3, seed=19)
+    n = _spread_state(M)
+    got = smol.rhs(t(U), t(V), 0.01, t(n)).cpu().numpy()
+    idx = np.array([0, 1, 2, 1000, M // 2, M - 3, M - 2, M - 1])
+    ref = oracle.rhs_entries(U, V, 0.01, n, idx)
+    err = np.abs(got[idx] - ref).max() / np.abs(got).max()
+    say(f"rhs M={M}: sampled error vs oracle {err:.2e}")
+    assert err < TOL
+    M += 1
+    U, V = W.random_factors(M, 1, seed=20)
+    n = t(W.random_state(M, seed=21))
+    with pytest.raises(smol.SmolError) as e:
+        smol.rhs(t(U), t(V), 0.01, n)
+    assert e.value.code == smol.EUNSUPPORTED
+    with pytest.raises(smol.SmolError) as e:
+        smol.integrate(t(U), t(V), 0.01, n, 1.0, 1e-6, 1e-12, raise_on_error=True)
+    assert e.value.code == smol.EUNSUPPORTED
 
 
 def test_rhs_rank4_equals_rank3(smol):
