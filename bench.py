@@ -196,13 +196,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--t-end", type=float, default=None, help="shorter runs (profiling)")
-    ap.add_argument("--workload", choices=["single", "batch", "learned", "kernels", "precision"],
+    ap.add_argument("--workload", choices=["single", "batch", "learned", "kernels", "precision",
+                                           "sizes"],
                     default="single",
                     help="single: the M=65536 DP5 instance (default); batch: the 256-instance "
                          "sweep; learned: train the step proposer, then learned vs PI at "
                          "M=262144; kernels: --steps launches of each RHS kernel plus a 64 MiB "
                          "device copy (for hardware-counter runs); precision: the float-float "
-                         "convolutions against the oracle's trajectory windows and FP64 to t=1e3")
+                         "convolutions against the oracle's trajectory windows and FP64 to t=1e3; "
+                         "sizes: the right-hand side and the stage kernels at M = 2^12..2^19")
     ap.add_argument("--no-accuracy-check", action="store_true",
                     help="skip the tight reference run that selects rtol (profiling)")
     ap.add_argument("--train-instances", type=int, default=512)
@@ -232,6 +234,8 @@ def main():
         return bench_kernels(args, smol, W, torch, dev)
     if args.workload == "precision":
         return bench_precision(args, smol, W, torch, dev)
+    if args.workload == "sizes":
+        return bench_sizes(args, smol, W, torch, dev)
     c = W.WORKLOADS["single-large"]
     t_end = args.t_end if args.t_end else c["t_end"]
     U, V, lam, n0 = W.workload_instance("single-large")
@@ -440,6 +444,52 @@ def bench_kernels(args, smol, W, torch, dev):
                       "copy_same_footprint": ceil,
                       "copy_bytes_each_way": nbytes}),
           flush=True)
+
+
+def bench_sizes(args, smol, W, torch, dev):
+    """The hot path against the size: for M = 2^12 .. 2^19 (transform
+    lengths 2^13 .. 2^20; the single-large kernel, rank 3, a = 0.45,
+    lam = 0.005, at an exponential state), the standalone right-hand side
+    and the integrator's DP5 stage kernels timed live (200 launches each),
+    their fraction of HBM peak on the algorithmic bytes, a plain copy of the
+    right-hand side's bytes as the ceiling at that footprint, and DP5 step
+    attempts per second (a run of 400 attempts from the monodisperse start)."""
+    import numpy as np
+    c = W.WORKLOADS["single-large"]
+    rows = []
+    for logM in range(12, 20):
+        M = 1 << logM
+        L = 1 << int(np.ceil(np.log2(2 * M - 2)))
+        U, V = W.brownian_rank3(M, c["a"])
+        Ud, Vd = torch.from_numpy(U).to(dev), torch.from_numpy(V).to(dev)
+        nd = torch.from_numpy(W.exponential_start(M, M / 200.0)).to(dev)
+        rhs = smol.profile_rhs(Ud, Vd, c["lam"], nd, iters=200)
+        step = smol.profile_step(Ud, Vd, c["lam"], nd, method="dp5", iters=200)
+        rb, sb = rhs_bytes(M, 3, L), step_bytes(M, 3, L)
+        n0 = torch.from_numpy(W.monodisperse(M)).to(dev)
+        smol.integrate(Ud, Vd, c["lam"], n0, 1e9, 1e-6, 1e-12, method="dp5", max_steps=16)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = smol.integrate(Ud, Vd, c["lam"], n0, 1e9, 1e-6, 1e-12, method="dp5",
+                               max_steps=400)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        attempts = st["n_accept"] + st["n_reject"]
+        row = {"M": M, "fft_length": L,
+               "rhs_ms": rhs["rhs"], "rhs_frac": rb["rhs"] / (rhs["rhs"] * 1e-3) / HBM_PEAK,
+               "rhs_evals_per_s": 1e3 / rhs["rhs"],
+               "copy_rhs_footprint_frac": copy_ceiling(torch, dev, rb["rhs"])["frac"],
+               "int_c_fused_ms": step["int_c_fused"],
+               "int_c_fused_frac": sb["int_c_fused"] / (step["int_c_fused"] * 1e-3) / HBM_PEAK,
+               "stage_kernels_ms_per_attempt": sum(step[k] * STEP_LAUNCHES[k]
+                                                   for k in STEP_LAUNCHES),
+               "attempts_per_s": attempts / dt, "ms_per_attempt": 1e3 * dt / attempts}
+        print(f"bench: sizes M=2^{logM}: {row}", file=sys.stderr, flush=True)
+        rows.append(row)
+        del Ud, Vd, nd, n0
+        smol.release_plans()
+    print(json.dumps({"workload": "sizes", "kernel": "rank-3 (i/j)^a+(j/i)^a+2, a=0.45, "
+                      "lam=0.005", "rows": rows}), flush=True)
 
 
 def bench_precision(args, smol, W, torch, dev):

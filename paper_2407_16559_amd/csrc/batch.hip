@@ -421,6 +421,8 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
                 live.push_back(i);
                 double est = hctl[i].h > 0 ? (hctl[i].t_end - hctl[i].t) / hctl[i].h : 1e9;
                 if (!(est < 1e9)) est = 1e9;
+                const double left = (double)(hctl[i].max_steps - hctl[i].attempts);
+                if (left < est) est = left;
                 if (est > most) most = est;
             }
             if (live.empty()) break;

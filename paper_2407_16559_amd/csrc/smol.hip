@@ -574,6 +574,10 @@ extern "C" int smol_integrate_ex(int64_t M, int32_t R, const double *U, const do
         if (c.done) break;
         double est = (c.h > 0) ? (c.t_end - c.t) / c.h : 1e9;
         if (!(est < 1e9)) est = 1e9;
+        // nor far beyond the attempt limit (surplus attempts return at entry,
+        // but each still costs its launches)
+        const double left = (double)(c.max_steps - c.attempts);
+        if (left < est) est = left;
         chunk = (int64_t)(0.8 * est / SMOL_GRAPH_ATTEMPTS) + 1;
         if (chunk > 64) chunk = 64;
         if (chunk < 1) chunk = 1;
