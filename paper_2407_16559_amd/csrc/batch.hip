@@ -426,7 +426,16 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
                 if (est > most) most = est;
             }
             if (live.empty()) break;
-            if (2 * live.size() <= ids.size()) {
+            // rebuild when half the instances have finished, or when every
+            // instance of some shape has: that shape's graph would only replay
+            // empty launches, and on a shared stream hold up a live shape
+            bool shape_done = false;
+            for (const auto &sh : br.shapes) {
+                bool any = false;
+                for (int i : live) any = any || br.logL[i] == sh.logL;
+                shape_done = shape_done || !any;
+            }
+            if (2 * live.size() <= ids.size() || shape_done) {
                 ids = live;
                 if ((rc = build_tables(br, ids, dfirst, downer, dactive, s))) break;
                 need_capture = true;
