@@ -441,7 +441,8 @@ extern "C" int smol_integrate_batch(int32_t n_inst, const smol_instance *inst, i
                 need_capture = true;
             }
             chunk = (int64_t)(0.5 * most / SMOL_GRAPH_ATTEMPTS) + 1;
-            if (chunk > 16) chunk = 16;
+            // at most 64 attempts of each shape between polls
+            if (chunk > 64 / SMOL_GRAPH_ATTEMPTS) chunk = 64 / SMOL_GRAPH_ATTEMPTS;
         }
         if (rc) break;
         if (hipMemcpyAsync(hctl, dctl, sizeof(IntegCtl) * n_inst, hipMemcpyDeviceToHost, s) != hipSuccess ||

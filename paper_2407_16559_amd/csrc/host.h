@@ -11,6 +11,7 @@
 
 #define SMOL_HIDDEN __attribute__((visibility("hidden")))
 #define SMOL_GRAPH_ATTEMPTS 16  // step attempts captured per graph
+static_assert(SMOL_GRAPH_ATTEMPTS >= 1 && SMOL_GRAPH_ATTEMPTS <= 64, "graph size");
 
 inline int hip_fail(hipError_t e, const char *what)
 {

@@ -579,7 +579,9 @@ extern "C" int smol_integrate_ex(int64_t M, int32_t R, const double *U, const do
         const double left = (double)(c.max_steps - c.attempts);
         if (left < est) est = left;
         chunk = (int64_t)(0.8 * est / SMOL_GRAPH_ATTEMPTS) + 1;
-        if (chunk > 64) chunk = 64;
+        // at most 256 attempts between polls: early in a run h is small and
+        // the estimate far too high, and every surplus attempt launches
+        if (chunk > 256 / SMOL_GRAPH_ATTEMPTS) chunk = 256 / SMOL_GRAPH_ATTEMPTS;
         if (chunk < 1) chunk = 1;
     }
     const IntegCtl &cf = c;
