@@ -107,6 +107,9 @@ struct IntegCtl {
     int32_t l2;
     double paper_s;
     int32_t has_src;  // Eq. (3) sources present
+    // an attempt has run whose accept / reject decision is still to be
+    // taken (by the next stage-2 column pass of a captured step)
+    int32_t pending;
 };
 
 // Step factor of the paper's rules (Sec. 2): Fehlberg's fifth-root rule
@@ -374,19 +377,27 @@ __device__ inline void prepare_attempt(IntegCtl &c, bool new_step)
     c.h = tn - c.t;
 }
 
-// Deterministic block reduction of epart rows: each thread sums a fixed
-// stride of rows, the wave butterfly adds the threads of a wave, then the
-// waves are added in order; every thread receives the totals.
-__device__ inline void block_sum_epart(const double *ep, int njobs, double *tot)
+// Deterministic block reduction of epart rows, in two parts so that a
+// kernel can request the rows before it knows whether it needs them.
+// epart_partial: the first SMOL_WG threads each sum a fixed stride of rows
+// (the others hold zeros).  epart_total (a workgroup of NT threads): the
+// wave butterfly adds the threads of a wave, then the waves are added in
+// order; waves beyond the first SMOL_WAVES add zeros, so any NT gives the
+// same totals.  Every thread receives them.
+__device__ inline void epart_partial(const double *ep, int njobs, double *acc)
 {
-    __shared__ double sh[SMOL_WAVES][SMOL_EPART];
     const int tid = threadIdx.x;
-    double acc[SMOL_EPART];
 #pragma unroll
     for (int q = 0; q < SMOL_EPART; ++q) acc[q] = 0.0;
-    for (int j = tid; j < njobs; j += SMOL_WG)
+    if (tid < SMOL_WG)
+        for (int j = tid; j < njobs; j += SMOL_WG)
 #pragma unroll
-        for (int q = 0; q < SMOL_EPART; ++q) acc[q] += ep[(int64_t)j * SMOL_EPART + q];
+            for (int q = 0; q < SMOL_EPART; ++q) acc[q] += ep[(int64_t)j * SMOL_EPART + q];
+}
+template <int NT = SMOL_WG>
+__device__ inline void epart_total(double *acc, double *tot)
+{
+    __shared__ double sh[NT / 64][SMOL_EPART];
 #pragma unroll
     for (int q = 0; q < SMOL_EPART; ++q) acc[q] = wave_sum(acc[q]);
     if (lane_id() == 0)
@@ -397,10 +408,16 @@ __device__ inline void block_sum_epart(const double *ep, int njobs, double *tot)
     for (int q = 0; q < SMOL_EPART; ++q) {
         double a = 0.0;
 #pragma unroll
-        for (int w = 0; w < SMOL_WAVES; ++w) a += sh[w][q];
+        for (int w = 0; w < NT / 64; ++w) a += sh[w][q];
         tot[q] = a;
     }
     __syncthreads();
+}
+__device__ inline void block_sum_epart(const double *ep, int njobs, double *tot)
+{
+    double acc[SMOL_EPART];
+    epart_partial(ep, njobs, acc);
+    epart_total<SMOL_WG>(acc, tot);
 }
 
 // ---- learned step proposer ----------------------------------------------
@@ -521,19 +538,19 @@ __device__ inline void init_h_step(const IntegDev &I, int njobs)
     prepare_attempt(c, true);
 }
 
-// Accept / reject and the next step size after the last stage; run by one
-// whole workgroup.  PI control, or (learned mode) the proposer's
-// log(h_next/h) after an accepted step that did not follow a rejection,
-// with PI as the fallback after a rejection or for non-finite features.
-__device__ inline void controller_step(const IntegDev &I, int njobs)
+// Accept / reject and the next step size after the last stage, from the
+// attempt's reduced error partials tot.  PI control, or (learned mode) the
+// proposer's log(h_next/h) after an accepted step that did not follow a
+// rejection, with PI as the fallback after a rejection or for non-finite
+// features.  Called by a whole workgroup (the proposer's forward pass uses
+// every thread); thread 0 updates c, which may be the control block itself
+// or a workgroup's shared copy of it, and writes the attempt's log row when
+// log_row is set.
+__device__ inline void controller_decide(IntegCtl &c, const double *tot, int64_t M, bool log_row)
 {
-    IntegCtl &c = *I.ctl;
-    if (c.done) return;
-    double tot[SMOL_EPART];
-    block_sum_epart(I.epart, njobs, tot);
     const Tableau &T = c_tab[c.method];
     const int k = T.q + 1;
-    const double err = c.l2 ? sqrt(tot[0]) : rms_of(tot[0], I.M);
+    const double err = c.l2 ? sqrt(tot[0]) : rms_of(tot[0], M);
     const bool accept = err <= 1.0;
     const bool bad = isnan(err) || tot[5] > 0.0;
     // error history including this attempt (most recent first)
@@ -564,7 +581,7 @@ __device__ inline void controller_step(const IntegDev &I, int njobs)
     c.n_rhs += T.S - 1;
     for (int q = 0; q < 4; ++q) c.err_hist[q] = hist[q];
     c.n_hist = nh;
-    if (c.log && c.attempts <= c.log_cap) {
+    if (c.log && log_row && c.attempts <= c.log_cap) {
         double *row = c.log + (c.attempts - 1) * 9;
         row[0] = c.t;
         row[1] = c.h;
@@ -625,4 +642,15 @@ __device__ inline void controller_step(const IntegDev &I, int njobs)
         c.n_reject += 1;
         prepare_attempt(c, false);
     }
+}
+
+// The decision by its own one-workgroup kernel (batched runs): the error
+// rows reduced here, the control block updated in place.
+__device__ inline void controller_step(const IntegDev &I, int njobs)
+{
+    IntegCtl &c = *I.ctl;
+    if (c.done) return;
+    double tot[SMOL_EPART];
+    block_sum_epart(I.epart, njobs, tot);
+    controller_decide(c, tot, I.M, true);
 }

@@ -38,17 +38,65 @@ __global__ __launch_bounds__(64 * W) void k_phaseC(RhsPlanDev P, Epi ep, int nun
 
 // ---- integrator stages: the same phases, buffers from the control block ----
 
+__device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uniform_d(double v)
+{
+    return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                            __builtin_amdgcn_readfirstlane(__double2loint(v)));
+}
+
 // method: the run's tableau, passed by the host so that the coefficient
-// loads do not wait for the control block
-template <int N1, int N2, class T, int E, int W>
-__global__ __launch_bounds__(64 * W) void k_int_A(IntegDev I, int stage, int nunits, int method)
+// loads do not wait for the control block.
+//
+// CTRL (the stage-2 column pass of a captured step attempt): the control
+// block I.ctl holds the previous attempt, whose error rows are in I.epart
+// (njobs of them) when its flag `pending` is set.  Every workgroup takes that
+// attempt's accept / reject decision and the next step itself (the same
+// arithmetic in the same order, so the same result) and goes on with the
+// attempt it prepared; workgroup 0 stores the updated block to cout, which
+// the attempt's later kernels read and the next stage-2 pass takes as its
+// input (two blocks, alternating).  The error rows are requested before the
+// control block.
+template <int N1, int N2, class T, int E, int W, bool CTRL>
+__global__ __launch_bounds__(64 * W) void k_int_A(IntegDev I, int stage, int nunits, int method,
+                                                  IntegCtl *cout, int njobs)
 {
     using PA = PhaseA<N1, N2, T, E, W>;
     extern __shared__ cd lds[];
     const int unit = xcd_remap(blockIdx.x, gridDim.x);
     typename PA::Early e;  // twiddles and factors: requested before the control block
     if (unit < nunits) PA::early(plan_of_ws(I), unit, e);
-    const IntegCtl c = *I.ctl;  // one snapshot: all fields load together
+    IntegCtl c;
+    if constexpr (CTRL) {
+        __shared__ IntegCtl sc;
+        constexpr int NW = sizeof(IntegCtl) / 4;
+        double acc[SMOL_EPART];
+        epart_partial(I.epart, njobs, acc);
+        for (int i = threadIdx.x; i < NW; i += 64 * W)
+            ((uint32_t *)&sc)[i] = ((const uint32_t *)I.ctl)[i];
+        __syncthreads();
+        if (!sc.done && sc.pending) {
+            double tot[SMOL_EPART];
+            epart_total<64 * W>(acc, tot);
+            controller_decide(sc, tot, I.M, blockIdx.x == 0);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) sc.pending = sc.done ? 0 : 1;
+        __syncthreads();
+        if (blockIdx.x == 0)
+            for (int i = threadIdx.x; i < NW; i += 64 * W)
+                ((uint32_t *)cout)[i] = ((const uint32_t *)&sc)[i];
+        // what this pass reads of the block, as uniform values
+        c.done = uniform_i(sc.done);
+        c.cur = uniform_i(sc.cur);
+        c.kp = uniform_i(sc.kp);
+        c.has_src = uniform_i(sc.has_src);
+        c.h = uniform_d(sc.h);
+        c.h0 = uniform_d(sc.h0);
+        c.lam = uniform_d(sc.lam);
+    } else {
+        c = *I.ctl;  // one snapshot: all fields load together
+    }
     if (c.done) return;
     const Tableau &tab = c_tab[method];
     const RhsPlanDev P = plan_of(I, c);
@@ -178,12 +226,17 @@ struct RhsC {
 };
 struct IntA {
     template <int N1, int N2, class T, int E, int W>
-    static int run(const IntegDev &I, int stage, int method, hipStream_t s)
+    static int run(const IntegDev &I, int stage, int method, IntegCtl *cout, int njobs,
+                   hipStream_t s)
     {
         using A = PhaseA<N1, N2, T, E, W>;
         const int n = A::units(I.R);
-        hipLaunchKernelGGL((k_int_A<N1, N2, T, E, W>), dim3(n), dim3(A::NT), sizeof(cd) * A::LDS,
-                           s, I, stage, n, method);
+        if (cout)
+            hipLaunchKernelGGL((k_int_A<N1, N2, T, E, W, true>), dim3(n), dim3(A::NT),
+                               sizeof(cd) * A::LDS, s, I, stage, n, method, cout, njobs);
+        else
+            hipLaunchKernelGGL((k_int_A<N1, N2, T, E, W, false>), dim3(n), dim3(A::NT),
+                               sizeof(cd) * A::LDS, s, I, stage, n, method, cout, njobs);
         return SMOL_OK;
     }
 };

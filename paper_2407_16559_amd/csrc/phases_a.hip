@@ -8,9 +8,9 @@ SMOL_HIDDEN int launch_rhs_A(int logL, int precision, int v, const RhsPlanDev &P
 }
 
 SMOL_HIDDEN int launch_int_A(int logL, int precision, int v, const IntegDev &I, int stage,
-                             int method, hipStream_t s)
+                             int method, IntegCtl *cout, int njobs, hipStream_t s)
 {
-    return with_variant<IntA, PH_A>(logL, precision, v, I, stage, method, s);
+    return with_variant<IntA, PH_A>(logL, precision, v, I, stage, method, cout, njobs, s);
 }
 
 SMOL_HIDDEN int launch_bat_A(int logL, int precision, int v, const BatchDev &B, int base, int count,

@@ -143,8 +143,10 @@ SMOL_HIDDEN int launch_rhs_B(int logL, int precision, int v, const RhsPlanDev &P
                              hipStream_t s);
 SMOL_HIDDEN int launch_rhs_C(int logL, int precision, int v, const RhsPlanDev &P, const Epi &ep,
                              hipStream_t s);
+// cout non-null: the stage-2 pass that also takes the previous attempt's
+// decision (njobs error rows) and stores the updated control block there.
 SMOL_HIDDEN int launch_int_A(int logL, int precision, int v, const IntegDev &I, int stage,
-                             int method, hipStream_t s);
+                             int method, IntegCtl *cout, int njobs, hipStream_t s);
 SMOL_HIDDEN int launch_int_B(int logL, int precision, int v, const IntegDev &I, int stage,
                              int jobs_a, int jobs_c, hipStream_t s);
 SMOL_HIDDEN int launch_int_C(int logL, int precision, int v, bool fuse, const IntegDev &I,

@@ -3,6 +3,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -42,7 +43,6 @@ __global__ void k_from_tr(const double *src, double *dst, int64_t M, int logL)
 
 __global__ __launch_bounds__(SMOL_WG) void k_init_h0(IntegDev I, int njobs) { init_h0_step(I, njobs); }
 __global__ __launch_bounds__(SMOL_WG) void k_init_h(IntegDev I, int njobs) { init_h_step(I, njobs); }
-__global__ __launch_bounds__(SMOL_WG) void k_ctrl(IntegDev I, int njobs) { controller_step(I, njobs); }
 
 // Resume from a checkpoint: the smallest step at the state's time, then the
 // next attempt prepared as the interrupted run would have prepared it (after
@@ -282,12 +282,24 @@ int launch_rhs(const Plan *p, const RhsPlanDev &P, const Pro &in, const Epi &ep,
 // One stage (or starting-step evaluation) of the integrator.  Stages 0..2
 // run A, B, C; from stage 3 on the column pass was done by the previous
 // stage's fused finish, so only B and C run; the finish of stages
-// 2..S-1 is fused with the next column pass.
-int launch_stage(const Plan *p, const IntegDev &I, int method, int stage, int S, hipStream_t s)
+// 2..S-1 is fused with the next column pass.  decide_from (stage 2 of a
+// captured attempt): the control block holding the previous attempt, whose
+// decision the column pass takes before it, storing the result to I.ctl.
+int launch_stage(const Plan *p, const IntegDev &I, int method, int stage, int S, hipStream_t s,
+                 IntegCtl *decide_from = nullptr)
 {
     int rc;
-    if (stage <= 2 && (rc = launch_int_A(p->logL, p->precision, p->var[0], I, stage, method, s)))
-        return rc;
+    if (stage <= 2) {
+        if (decide_from) {
+            IntegDev Ii = I;
+            Ii.ctl = decide_from;
+            rc = launch_int_A(p->logL, p->precision, p->var[0], Ii, stage, method, I.ctl,
+                              p->dC.jobs, s);
+        } else {
+            rc = launch_int_A(p->logL, p->precision, p->var[0], I, stage, method, nullptr, 0, s);
+        }
+        if (rc) return rc;
+    }
     if ((rc = launch_int_B(p->logL, p->precision, p->var[1], I, stage, p->dA.jobs, p->dC.jobs, s)))
         return rc;
     const bool fuse = stage >= 2 && stage < S;
@@ -303,7 +315,8 @@ int alloc_integ(Plan *p)
     p->Mt = p->M > half + 1 ? p->M : half + 1;
     if (hipMalloc(&p->ibuf, sizeof(double) * (size_t)p->Mt * 11) != hipSuccess) return SMOL_ENOMEM;
     if (hipMalloc(&p->uvt, sizeof(double) * (size_t)p->Mt * 2 * p->R) != hipSuccess) return SMOL_ENOMEM;
-    if (hipMalloc(&p->ctl, sizeof(IntegCtl)) != hipSuccess) return SMOL_ENOMEM;
+    // two control blocks: captured attempts alternate between them
+    if (hipMalloc(&p->ctl, 2 * sizeof(IntegCtl)) != hipSuccess) return SMOL_ENOMEM;
     HIP_TRY(hipHostMalloc(&p->host, sizeof(IntegCtl), hipHostMallocDefault));
     HIP_TRY(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
     return SMOL_OK;
@@ -335,8 +348,11 @@ IntegDev integ_dev(const Plan *p, const DevRoots *r)
     return I;
 }
 
-// Capture SMOL_GRAPH_ATTEMPTS step attempts (stages 2..S, controller) as
-// one graph.
+// Capture SMOL_GRAPH_ATTEMPTS step attempts (stages 2..S) as one graph.
+// Each attempt's stage-2 column pass first takes the previous attempt's
+// decision: attempt a reads control block a % 2 and writes block
+// (a + 1) % 2, which its later kernels read.  With an even number of
+// attempts per graph, block 0 holds the latest state between replays.
 int get_step_graph(Plan *p, const IntegDev &I, int method, hipGraphExec_t *out)
 {
     if (p->graph[method]) {
@@ -347,11 +363,12 @@ int get_step_graph(Plan *p, const IntegDev &I, int method, hipGraphExec_t *out)
     hipGraph_t g;
     HIP_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
     int rc = SMOL_OK;
-    const int nC = p->dC.jobs;
+    static_assert(SMOL_GRAPH_ATTEMPTS % 2 == 0, "control blocks alternate per attempt");
     for (int a = 0; a < SMOL_GRAPH_ATTEMPTS; ++a) {
+        IntegDev Ia = I;
+        Ia.ctl = p->ctl + ((a + 1) & 1);
         for (int st = 2; st <= S && rc == SMOL_OK; ++st)
-            rc = launch_stage(p, I, method, st, S, p->cap);
-        hipLaunchKernelGGL(k_ctrl, dim3(1), dim3(SMOL_WG), 0, p->cap, I, nC);
+            rc = launch_stage(p, Ia, method, st, S, p->cap, st == 2 ? p->ctl + (a & 1) : nullptr);
     }
     hipError_t e = hipStreamEndCapture(p->cap, &g);
     if (rc) return rc;
@@ -695,8 +712,10 @@ extern "C" int smol_profile_rhs(int64_t M, int32_t R, const double *U, const dou
 // iters times back to back between HIP events.  Relaunching a stage kernel
 // recomputes the same workspaces from the same inputs, except that the fused
 // finish of stage 3 reads and rewrites the stage state, which stays finite
-// for a stable step; the run's control block is never advanced (no
-// controller launch), so every launch does its full work.
+// for a stable step.  The stage-2 pass is timed as a captured attempt runs
+// it, taking the previous attempt's decision, with its result stored to the
+// second control block: the run's block is never advanced, so every launch
+// does the same full work.
 extern "C" int smol_profile_step(int64_t M, int32_t R, const double *U, const double *V,
                                  double lambda, const double *n0, int32_t method, int32_t iters,
                                  float *ms_out, void *stream)
@@ -739,8 +758,14 @@ extern "C" int smol_profile_step(int64_t M, int32_t R, const double *U, const do
     hipEvent_t ev[5];
     for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
     HIP_TRY(hipEventRecord(ev[0], s));
+    // the stage-2 pass as a captured attempt runs it: taking the decision of
+    // the attempt just evaluated (block 0, marked pending) and storing the
+    // result to block 1, so that every launch repeats the same work
+    c.pending = 1;
+    HIP_TRY(hipMemcpyAsync((char *)p->ctl + offsetof(IntegCtl, pending), &c.pending,
+                           sizeof(c.pending), hipMemcpyHostToDevice, s));
     for (int i = 0; i < iters && !rc; ++i)
-        rc = launch_int_A(p->logL, SMOL_FP64, p->var[0], I, 2, method, s);
+        rc = launch_int_A(p->logL, SMOL_FP64, p->var[0], I, 2, method, p->ctl + 1, nC, s);
     HIP_TRY(hipEventRecord(ev[1], s));
     for (int i = 0; i < iters && !rc; ++i)
         rc = launch_int_B(p->logL, SMOL_FP64, p->var[1], I, 3, p->dA.jobs, nC, s);
