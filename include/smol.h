@@ -367,9 +367,13 @@ int smol_profile_rhs(int64_t M, int32_t R, const double *U, const double *V,
  * attempt replays; Sec. 2, Eq. (5), with the right-hand side of Eq. (4)).
  * Runs the starting step and one attempt's stages of `method` (SMOL_BS32 or
  * SMOL_DP54, FP64, rtol 1e-6, atol 1e-12) from the state n0 (device, M
- * doubles, natural layout) without a controller launch, then launches each
- * kernel `iters` times back to back between HIP events on `stream`:
- *   ms_out[0] column pass of stage 2 (forms y_2 = n + h a_21 k_1);
+ * doubles, natural layout) without taking that attempt's decision, then
+ * launches each kernel `iters` times back to back between HIP events on
+ * `stream`:
+ *   ms_out[0] column pass of stage 2 as a step attempt runs it: the previous
+ *             attempt's accept / reject decision, then y_2 = n + h a_21 k_1
+ *             and its transforms (the decision's result goes to a second
+ *             control block, so every launch repeats the same work);
  *   ms_out[1] row-pair spectral pass;
  *   ms_out[2] inverse column pass + finish of stage 3 fused with the stage
  *             4 state, its reductions and the next column pass;
