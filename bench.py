@@ -70,7 +70,8 @@ def step_bytes(M, R, L):
     """Algorithmic HBM bytes of the integrator's stage kernels in a DP5(4)
     attempt (FP64):
       int_a        column pass of stage 2: reads n, k_1, U, V; writes y_2 and
-                   R packed spectra;
+                   R packed spectra (it also reads the previous attempt's
+                   error rows for its decision, 16 KiB, not counted);
       int_b        row-pair pass: reads the spectra, writes the packed inverse
                    input;
       int_c_fused  finish of stage 3 fused with the next column pass: reads the
