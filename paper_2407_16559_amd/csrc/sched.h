@@ -39,6 +39,9 @@ int run_variant(int v, Args &&...args)
     constexpr int E0 = fft_default_e(N);
     constexpr bool tuned = std::is_same<T, cd>::value && LOGL >= SMOL_TUNE_MIN_LOGL;
     constexpr bool alt_e = tuned && fft_valid_e(N, 4) && E0 != 4;
+    // float-float row-pair pass: the radix-4 form only (see ff_schedule)
+    constexpr bool ff_b = std::is_same<T, cff>::value && PH == PH_B &&
+                          LOGL >= SMOL_TUNE_MIN_LOGL && fft_valid_e(N, 4) && E0 != 4;
     switch (v) {
     case 0: return F::template run<N1, N2, T, E0, 4>(args...);
     case 1:
@@ -48,10 +51,19 @@ int run_variant(int v, Args &&...args)
         if constexpr (alt_e) return F::template run<N1, N2, T, 4, 4>(args...);
         return SMOL_EUNSUPPORTED;
     case 3:
-        if constexpr (alt_e) return F::template run<N1, N2, T, 4, 8>(args...);
+        if constexpr (alt_e || ff_b) return F::template run<N1, N2, T, 4, 8>(args...);
         return SMOL_EUNSUPPORTED;
     default: return SMOL_EUNSUPPORTED;
     }
+}
+
+// Schedule of float-float plans (not tuned): the row-pair pass with radix-4
+// butterflies (variant 3) where its rows allow it (N2 <= 256), which keeps
+// its float-float registers from spilling; everything else variant 0.
+inline void ff_schedule(int logL, int *v)
+{
+    v[0] = v[2] = 0;
+    v[1] = (logL >= SMOL_TUNE_MIN_LOGL && (1 << split_log_n2(logL)) <= 256) ? 3 : 0;
 }
 
 template <class F, int PH, class... Args>

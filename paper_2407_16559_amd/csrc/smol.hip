@@ -213,8 +213,9 @@ int get_plan(int64_t M, int R, int precision, Plan **out)
     p->red = p->red_part + (size_t)N2 * R * 4;
     p->epart = p->red + (size_t)R * 4;
     sched_init();
-    static const int v0[3] = {0, 0, 0};
-    int rc = set_plan_sched(p, precision == SMOL_FP64 ? g_sched[logL] : v0);
+    int vff[3];
+    ff_schedule(logL, vff);
+    int rc = set_plan_sched(p, precision == SMOL_FP64 ? g_sched[logL] : vff);
     if (rc) {
         free_plan(p);
         return rc;
@@ -824,8 +825,11 @@ int set_schedule_locked(int logL, const int32_t *v)
 SMOL_HIDDEN void schedule_of(int logL, int precision, int *v)
 {
     sched_init();
-    for (int k = 0; k < 3; ++k)
-        v[k] = (precision == SMOL_FP64 && logL >= 6 && logL <= SMOL_LOG_LMAX) ? g_sched[logL][k] : 0;
+    if (precision != SMOL_FP64) {
+        ff_schedule(logL, v);
+        return;
+    }
+    for (int k = 0; k < 3; ++k) v[k] = (logL >= 6 && logL <= SMOL_LOG_LMAX) ? g_sched[logL][k] : 0;
 }
 
 extern "C" int smol_set_schedule(int32_t logL, const int32_t *variants)
