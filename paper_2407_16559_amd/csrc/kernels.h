@@ -12,7 +12,7 @@ __global__ __launch_bounds__(64 * W) void k_phaseA(RhsPlanDev P, Pro in, int nun
 {
     extern __shared__ cd lds[];
     const int unit = xcd_remap(blockIdx.x, gridDim.x);
-    if (unit < nunits) PhaseA<N1, N2, T, E, W>::run(P, in, unit, (T *)lds);
+    if (unit < nunits) SMOL_PHASE_CALL(T, PhaseA<N1, N2, T, E, W>::run(P, in, unit, (T *)lds));
 }
 
 template <int N1, int N2, class T, int E, int W>
@@ -25,7 +25,7 @@ __global__ __launch_bounds__(64 * W) void k_phaseB(RhsPlanDev P, int red_jobs)
         if (red_jobs > 0) finalize_reductions<64 * W>(P, red_jobs);
         return;
     }
-    PhaseB<N1, N2, T, E, W>::run(P, u, (T *)lds);
+    SMOL_PHASE_CALL(T, PhaseB<N1, N2, T, E, W>::run(P, u, (T *)lds));
 }
 
 template <int N1, int N2, class T, int E, int W>
@@ -33,7 +33,8 @@ __global__ __launch_bounds__(64 * W) void k_phaseC(RhsPlanDev P, Epi ep, int nun
 {
     extern __shared__ cd lds[];
     const int unit = xcd_remap(blockIdx.x, gridDim.x);
-    if (unit < nunits) PhaseC<N1, N2, T, E, W>::template run<false>(P, ep, unit, (T *)lds);
+    if (unit < nunits)
+        SMOL_PHASE_CALL(T, PhaseC<N1, N2, T, E, W>::template run<false>(P, ep, unit, (T *)lds));
 }
 
 // ---- integrator stages: the same phases, buffers from the control block ----
@@ -101,7 +102,7 @@ __global__ __launch_bounds__(64 * W) void k_int_A(IntegDev I, int stage, int nun
     const Tableau &tab = c_tab[method];
     const RhsPlanDev P = plan_of(I, c);
     const Pro in = stage_pro(I, c, tab, stage);
-    if (unit < nunits) PA::run_with(P, in, unit, (T *)lds, e);
+    if (unit < nunits) SMOL_PHASE_CALL(T, PA::run_with(P, in, unit, (T *)lds, e));
 }
 
 // jobs_a / jobs_c: reduction partial rows written by the column pass (stages
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(64 * W) void k_int_B(IntegDev I, int stage, int job
         finalize_reductions<64 * W>(P, stage <= 2 ? jobs_a : jobs_c);
         return;
     }
-    PhaseB<N1, N2, T, E, W>::run(P, u, (T *)lds);
+    SMOL_PHASE_CALL(T, PhaseB<N1, N2, T, E, W>::run(P, u, (T *)lds));
 }
 
 // The packed columns, twiddles and column-pass factors do not depend on the
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(64 * W) void k_int_C(IntegDev I, int stage, int nun
     const Tableau &tab = c_tab[method];
     const RhsPlanDev P = plan_of(I, c);
     const Epi ep = stage_epi(I, c, tab, stage);
-    if (unit < nunits) PC::template run_with<FUSE>(P, ep, unit, (T *)lds, e);
+    if (unit < nunits) SMOL_PHASE_CALL(T, PC::template run_with<FUSE>(P, ep, unit, (T *)lds, e));
 }
 
 // ---- batched stage kernels: blocks [base, base + gridDim) of one shape -------
@@ -155,7 +156,7 @@ __global__ __launch_bounds__(64 * W) void kb_A(BatchDev B, int base, int stage, 
     if (c.done) return;
     const RhsPlanDev P = plan_of(I, c);
     const Pro in = stage_pro(I, c, c_tab[method], stage);
-    PhaseA<N1, N2, T, E, W>::run(P, in, blk - B.first[0][b], (T *)lds);
+    SMOL_PHASE_CALL(T, PhaseA<N1, N2, T, E, W>::run(P, in, blk - B.first[0][b], (T *)lds));
 }
 
 template <int N1, int N2, class T, int E, int W>
@@ -173,7 +174,7 @@ __global__ __launch_bounds__(64 * W) void kb_B(BatchDev B, int base, int stage)
         finalize_reductions<64 * W>(P, stage <= 2 ? B.redA[b] : B.nC[b]);
         return;
     }
-    PhaseB<N1, N2, T, E, W>::run(P, unit, (T *)lds);
+    SMOL_PHASE_CALL(T, PhaseB<N1, N2, T, E, W>::run(P, unit, (T *)lds));
 }
 
 template <int N1, int N2, class T, int E, int W, bool FUSE>
@@ -187,7 +188,8 @@ __global__ __launch_bounds__(64 * W) void kb_C(BatchDev B, int base, int stage, 
     if (c.done) return;
     const RhsPlanDev P = plan_of(I, c);
     const Epi ep = stage_epi(I, c, c_tab[method], stage);
-    PhaseC<N1, N2, T, E, W>::template run<FUSE>(P, ep, blk - B.first[2][b], (T *)lds);
+    SMOL_PHASE_CALL(T, PhaseC<N1, N2, T, E, W>::template run<FUSE>(P, ep, blk - B.first[2][b],
+                                                                   (T *)lds));
 }
 
 // ---- launch functors (used through with_variant) ----------------------------

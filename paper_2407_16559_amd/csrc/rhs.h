@@ -41,6 +41,19 @@
 #pragma once
 #include "fft.h"
 
+// A call of one of a phase's large member functions.  The float-float bodies
+// are beyond the inliner's size limit, and an out-of-line call passes the
+// tile state through the stack (scratch memory), so for that type the call is
+// forced inline; FP64 calls are left to the inliner, which inlines them.
+#define SMOL_PHASE_CALL(C, ...)                  \
+    do {                                         \
+        if constexpr (__is_same(C, cff)) {       \
+            [[clang::always_inline]] __VA_ARGS__; \
+        } else {                                 \
+            __VA_ARGS__;                         \
+        }                                        \
+    } while (0)
+
 enum { A_GIVEN = 0, A_COMBINE = 1 };
 enum { C_RHS = 0, C_STAGE = 1, C_LAST = 2, C_INIT0 = 3, C_INIT1 = 4 };
 #define SMOL_MAX_STAGE 8
@@ -188,7 +201,7 @@ struct PhaseA {
     {
         Early e;
         early(P, unit, e);
-        run_with(P, in, unit, lds, e);
+        SMOL_PHASE_CALL(C, run_with(P, in, unit, lds, e));
     }
 
     __device__ static void run_with(const RhsPlanDev &P, const Pro &in, int unit, C *lds, Early &e)
@@ -470,7 +483,7 @@ struct PhaseC {
     {
         Early e;
         early<FUSE>(P, unit, e);
-        run_with<FUSE>(P, ep, unit, lds, e);
+        SMOL_PHASE_CALL(C, run_with<FUSE>(P, ep, unit, lds, e));
     }
 
     template <bool FUSE>
@@ -729,7 +742,7 @@ struct PhaseC {
         const int lane = lane_id(), w = wave_id();
         if constexpr (FUSE) {
             const int job = w * F::B + lane / F::G;
-            if (job < NCOL * P.R) col_load(P, unit, job, e.pre);
+            if (job < NCOL * P.R) SMOL_PHASE_CALL(C, col_load(P, unit, job, e.pre));
         }
         if (w == 0) {
             const int f = lane / F::G, g = lane % F::G;
@@ -754,7 +767,7 @@ struct PhaseC {
             if (job < nj) {
                 int jj, al, n2;
                 col_job(P, unit, job, jj, al, n2);
-                if (r0 > 0) col_load(P, unit, job, pre);
+                if (r0 > 0) SMOL_PHASE_CALL(C, col_load(P, unit, job, pre));
                 C v[F::E];
 #pragma unroll
                 for (int i = 0; i < F::E; ++i) {
