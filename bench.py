@@ -383,6 +383,14 @@ def bench_batch(args, smol, W, torch, dev):
     elapsed = (time.perf_counter() - t0) / args.steps
     n_acc = sum(s["n_accept"] for s in stats)
     n_rhs = sum(s["n_rhs"] for s in stats)
+    # the algorithmic bytes of every instance's right-hand sides (FP64
+    # three-kernel figure at its own M and transform length), per second of
+    # the batched run: how close the batch as a whole comes to HBM peak
+    alg = 0
+    for d, st in zip(insts, stats):
+        Mi, Ri = d["U"].shape[1], d["U"].shape[0]
+        Li = 1 << max(2 * Mi - 3, 1).bit_length()  # smallest power of 2 >= 2 M - 2
+        alg += st["n_rhs"] * rhs_bytes(Mi, Ri, Li)["rhs"]
     t0 = time.perf_counter()
     sample = list(range(0, len(insts), 16))
     for i in sample:
@@ -406,6 +414,8 @@ def bench_batch(args, smol, W, torch, dev):
         "speedup_vs_single_runs": single / elapsed,
         "accepted_steps_total": n_acc,
         "rhs_evals_per_s": n_rhs / elapsed,
+        "rhs_alg_GBps": alg / elapsed / 1e9,
+        "rhs_alg_frac_of_hbm_peak": alg / elapsed / HBM_PEAK,
         "max_accepted_steps_one_instance": max(s["n_accept"] for s in stats),
         "all_ok": all(s["status"] == 0 for s in stats),
     }
