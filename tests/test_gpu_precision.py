@@ -92,9 +92,9 @@ def test_precision_workload_trajectory(smol, name, kernel, a, lam):
     assert err < 1e-6
 
 
-@pytest.mark.parametrize("M", [131072, 262144])
+@pytest.mark.parametrize("M", [131072, 262144, 524288])
 def test_fp32x2_integration_long_transform(smol, M):
-    """DP5 with float-float convolutions at L = 2^18 and 2^19 (monodisperse
+    """DP5 with float-float convolutions at L = 2^18, 2^19 and 2^20 (monodisperse
     start, rank-3 kernel a = 0.45, lam = 0.005, t = 20): within the
     trajectory bar of the FP64 run, with the same step counts to within
     two."""
