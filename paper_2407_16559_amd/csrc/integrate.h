@@ -542,9 +542,10 @@ __device__ inline void init_h_step(const IntegDev &I, int njobs)
 // attempt's reduced error partials tot.  PI control, or (learned mode) the
 // proposer's log(h_next/h) after an accepted step that did not follow a
 // rejection, with PI as the fallback after a rejection or for non-finite
-// features.  Called by a whole workgroup (the proposer's forward pass uses
-// every thread); thread 0 updates c, which may be the control block itself
-// or a workgroup's shared copy of it, and writes the attempt's log row when
+// features.  Called by every thread of a workgroup (the proposer's forward
+// pass uses them all, and a barrier separates their reads of c from the
+// update); thread 0 updates c, which may be the control block itself or a
+// workgroup's shared copy of it, and writes the attempt's log row when
 // log_row is set.
 __device__ inline void controller_decide(IntegCtl &c, const double *tot, int64_t M, bool log_row)
 {
@@ -575,6 +576,9 @@ __device__ inline void controller_decide(IntegCtl &c, const double *tot, int64_t
             }
         }
     }
+    // every thread has read c (its branches above depend on it) before
+    // thread 0 updates it
+    __syncthreads();
     if (threadIdx.x) return;
     c.err = err;
     c.attempts += 1;

@@ -76,12 +76,15 @@ __global__ __launch_bounds__(64 * W) void k_int_A(IntegDev I, int stage, int nun
         for (int i = threadIdx.x; i < NW; i += 64 * W)
             ((uint32_t *)&sc)[i] = ((const uint32_t *)I.ctl)[i];
         __syncthreads();
+        // Every thread reads the flags before any thread writes the block:
+        // the decision's writes follow the barrier inside epart_total, and
+        // the flag update follows the barrier below on both paths.
         if (!sc.done && sc.pending) {
             double tot[SMOL_EPART];
             epart_total<64 * W>(acc, tot);
             controller_decide(sc, tot, I.M, blockIdx.x == 0);
-            __syncthreads();
         }
+        __syncthreads();
         if (threadIdx.x == 0) sc.pending = sc.done ? 0 : 1;
         __syncthreads();
         if (blockIdx.x == 0)
