@@ -85,6 +85,13 @@ def step_bytes(M, R, L):
             "int_c_last": 8 * L + 64 * M + 8 * M * R}
 
 
+def fft_length(M):
+    """Transform length the library uses for M sizes: the smallest power of
+    two >= 2 M - 2 (the linear convolution of two length-(M-1) inputs fits),
+    at least 2^6."""
+    return 1 << max(6, max(2 * M - 3, 1).bit_length())
+
+
 def min_bytes(M, R):
     """Compulsory HBM bytes of one right-hand side (FP64): read n, U and V
     once and write S, with no intermediate spectra."""
@@ -279,8 +286,7 @@ def main():
     # live per-kernel timing (HIP events on the stream the kernels run on) of
     # the integrator's stage kernels at the run's final state; the dominant
     # kernel is the one with the largest share of an attempt
-    logL = int(np.ceil(np.log2(2 * M - 2)))
-    L = 1 << logL
+    L = fft_length(M)
     prof = smol.profile_step(Ud, Vd, lam, out.clone(), method="dp5", iters=200)
     nbytes = step_bytes(M, R, L)
     dom = max(STEP_LAUNCHES, key=lambda k: prof[k] * STEP_LAUNCHES[k])
@@ -389,7 +395,7 @@ def bench_batch(args, smol, W, torch, dev):
     alg = 0
     for d, st in zip(insts, stats):
         Mi, Ri = d["U"].shape[1], d["U"].shape[0]
-        Li = 1 << max(2 * Mi - 3, 1).bit_length()  # smallest power of 2 >= 2 M - 2
+        Li = fft_length(Mi)
         alg += st["n_rhs"] * rhs_bytes(Mi, Ri, Li)["rhs"]
     t0 = time.perf_counter()
     sample = list(range(0, len(insts), 16))
@@ -431,7 +437,7 @@ def bench_kernels(args, smol, W, torch, dev):
     import numpy as np
     U, V, lam, n0 = W.workload_instance("single-large")
     M, R = U.shape[1], U.shape[0]
-    L = 1 << int(np.ceil(np.log2(2 * M - 2)))
+    L = fft_length(M)
     Ud, Vd, nd = (torch.from_numpy(x).to(dev) for x in (U, V, W.exponential_start(M, 300.0)))
     prof = smol.profile_rhs(Ud, Vd, lam, nd, iters=args.steps)
     prof_step = smol.profile_step(Ud, Vd, lam, nd, method="dp5", iters=args.steps)
@@ -470,7 +476,7 @@ def bench_sizes(args, smol, W, torch, dev):
     rows = []
     for logM in range(12, 20):
         M = 1 << logM
-        L = 1 << int(np.ceil(np.log2(2 * M - 2)))
+        L = fft_length(M)
         U, V = W.brownian_rank3(M, c["a"])
         Ud, Vd = torch.from_numpy(U).to(dev), torch.from_numpy(V).to(dev)
         nd = torch.from_numpy(W.exponential_start(M, M / 200.0)).to(dev)

@@ -48,3 +48,16 @@ def test_recorded_traffic_follows_the_source_hash(monkeypatch):
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
     assert bench.recorded_traffic("int_c_fused") is None
     assert bench.recorded_traffic("phase_a") is None
+
+
+def test_transform_length_rule():
+    """The transform length bench.py prices a size at: the smallest power of
+    two >= 2 M - 2 (two length-(M-1) inputs convolve without wrap-around),
+    at least 2^6, as the library chooses it."""
+    for M, L in [(1, 64), (2, 64), (33, 64), (34, 128), (4096, 8192), (4097, 8192),
+                 (4098, 16384), (65536, 1 << 17), (65537, 1 << 17), (65538, 1 << 18),
+                 ((1 << 19) + 1, 1 << 20)]:
+        assert bench.fft_length(M) == L, M
+    for M in range(2, 3000):
+        L = bench.fft_length(M)
+        assert L >= 2 * M - 2 and (L == 64 or L // 2 < 2 * M - 2)
